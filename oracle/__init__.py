@@ -1,0 +1,8 @@
+"""FP64 CPU oracle of the Fourier ADI hot path (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library.
+"""
+
+from .fourier_adi import *  # noqa: F401,F403
+from .fourier_adi import __all__  # noqa: F401
