@@ -1,0 +1,186 @@
+/*
+ * graphic.h -- C ABI of the MI355X Fourier ADI library (libgraphic.so).
+ *
+ * The operations follow Hagelberg et al. 2016, "The Geneva Reduction and
+ * Analysis Pipeline for High-contrast Imaging of planetary Companions"
+ * (MNRAS, arXiv:1510.04331):
+ *   - graphic_shift:      Sect. 3.3.1, Fourier shift (2-D shift equation):
+ *                         FT of the zero-padded frame, multiplication by the
+ *                         phasor exp(-i 2 pi (nu_x a + nu_y b)), inverse FT.
+ *   - graphic_rotate:     Sect. 3.4, rotation as three Fourier shears
+ *                         R = S_x(-tan(theta/2)) S_y(sin theta) S_x(-tan(theta/2)).
+ *   - graphic_median:     Sect. 3.3 and 3.4, per-pixel median of a stack.
+ *   - graphic_adi_reduce: Sect. 3 (classical ADI): recentre every frame,
+ *                         take the per-pixel median PSF, subtract it,
+ *                         derotate by minus the parallactic angle and merge
+ *                         the frames with a per-pixel median.
+ *
+ * Conventions
+ *   - Frames are float32, row-major, x (column) fastest: cube[t][y][x].
+ *   - Frames are square, N x N, N even.  The working size P is a power of two
+ *     with N <= P <= 4096 (default: smallest power of two >= 2N).  The frame
+ *     sits at offset (P-N)/2 of the zero-padded P x P frame, so the centre of
+ *     rotation c = P/2 is frame pixel (N/2, N/2).
+ *   - A shift (dx, dy) moves the content toward larger x and y.
+ *   - A rotation by theta (degrees) turns the content counter-clockwise in the
+ *     (x right, y up) frame: content at c + u ends at c + R(theta) u.  For
+ *     |theta| > 90 an exact half-turn is applied first.
+ *   - The Nyquist bin of every one-dimensional transform gets the real phasor
+ *     cos(pi s), so every pass maps real lines to real lines.
+ *   - Arithmetic: float32 transforms; the phase arguments k*s/P are reduced
+ *     modulo one in float64; flux sums are float64.
+ *
+ * Memory and ownership
+ *   - Every data pointer is DEVICE memory owned by the caller (for example a
+ *     torch tensor's data_ptr()).  The library never allocates, frees or keeps
+ *     caller memory.  Scratch memory ("workspace") is caller-provided device
+ *     memory of at least graphic_workspace_size() bytes, 256-byte aligned.
+ *   - A context owns only its twiddle tables and the device it was made on.
+ *     It is not thread-safe: use one context per host thread.
+ *
+ * Execution and errors
+ *   - Calls enqueue work on the given HIP stream and return without waiting.
+ *   - Arguments are checked on the host before anything is enqueued: a null
+ *     required pointer, odd or out-of-range N, an invalid P, T < 1, a too-small
+ *     or misaligned workspace, or partially overlapping input and output
+ *     return an error and launch nothing.  out == in is allowed where stated.
+ *   - A failed launch returns GRAPHIC_ERR_HIP.  Device-side faults surface at
+ *     the caller's next synchronisation.
+ *   - Non-finite input values are a precondition violation; the output is then
+ *     unspecified.
+ */
+#ifndef GRAPHIC_H
+#define GRAPHIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct graphic_ctx_s* graphic_ctx;
+
+/* An opaque HIP stream (hipStream_t); NULL is the default stream. */
+typedef void* graphic_stream;
+
+typedef enum {
+    GRAPHIC_OK = 0,
+    GRAPHIC_ERR_ARG = 1,          /* invalid argument; nothing launched */
+    GRAPHIC_ERR_UNSUPPORTED = 2,  /* valid but unsupported geometry */
+    GRAPHIC_ERR_WORKSPACE = 3,    /* workspace null, too small or misaligned */
+    GRAPHIC_ERR_HIP = 4,          /* a HIP runtime call failed */
+    GRAPHIC_ERR_NOMEM = 5         /* the context could not allocate its tables */
+} graphic_status;
+
+/* Operation codes for graphic_workspace_size. */
+enum {
+    GRAPHIC_OP_SHIFT = 0,
+    GRAPHIC_OP_ROTATE = 1,
+    GRAPHIC_OP_ADI = 2,
+    GRAPHIC_OP_MEDIAN = 3
+};
+
+/* Geometry of one cube. */
+typedef struct {
+    int64_t n_frames;   /* T >= 1 */
+    int32_t n;          /* N: even, 4 <= N <= 4096 */
+    int32_t pad;        /* P: power of two, N <= P <= 4096, 16 <= P; 0 => default */
+    uint32_t flags;     /* reserved, must be 0 */
+} graphic_geom;
+
+/* Create a context on HIP device `hip_device` (builds the twiddle tables on
+ * that device).  Returns GRAPHIC_ERR_HIP if the device is unusable. */
+graphic_status graphic_create(graphic_ctx* ctx, int hip_device);
+
+/* Release a context and its tables (NULL is ignored).  Work already enqueued
+ * with the context must have completed. */
+void graphic_destroy(graphic_ctx ctx);
+
+/* Static, human-readable name of a status code. */
+const char* graphic_status_string(graphic_status s);
+
+/* Library version string (static). */
+const char* graphic_version(void);
+
+/* Working size P that a geometry resolves to (pad, or the default for pad=0),
+ * or -1 if the geometry is invalid.  Host-only; needs no context. */
+int32_t graphic_resolved_pad(const graphic_geom* geom);
+
+/* Bytes of workspace that operation `op` (GRAPHIC_OP_*) needs for `geom`.
+ * Host-only; `ctx` may be NULL. */
+graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geom* geom,
+                                      size_t* bytes);
+
+/*
+ * Fourier shift of every frame (Sect. 3.3.1, 2-D shift equation).
+ *   in, out : [T][N][N] float32 device arrays; out == in is allowed.
+ *   dx, dy  : [T] float64 device arrays, content displacement in pixels.
+ *   flux    : NULL, or a [T][2] float64 device array receiving, per frame, the
+ *             sum of the input frame and the sum of the output frame.
+ *   ws      : device workspace of graphic_workspace_size(GRAPHIC_OP_SHIFT) bytes.
+ * Work: a column pass then a row pass, each a one-dimensional transform of the
+ * zero-extended line, a phase ramp and an inverse transform.
+ */
+graphic_status graphic_shift(graphic_ctx ctx, const graphic_geom* geom,
+                             const float* in, float* out,
+                             const double* dx, const double* dy,
+                             double* flux, void* ws, size_t ws_bytes,
+                             graphic_stream stream);
+
+/*
+ * Three-shear Fourier rotation of every frame (Sect. 3.4).
+ *   in, out   : [T][N][N] float32 device arrays; out == in is allowed.
+ *   theta_deg : [T] float64 device array, counter-clockwise angle in degrees.
+ *   flux      : NULL or [T][2] float64 (input sum, output sum) per frame.
+ *   ws        : graphic_workspace_size(GRAPHIC_OP_ROTATE) bytes.
+ */
+graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom,
+                              const float* in, float* out,
+                              const double* theta_deg, double* flux,
+                              void* ws, size_t ws_bytes, graphic_stream stream);
+
+/*
+ * Exact per-pixel median over the T frames of a float32 stack (the combiner
+ * of Sect. 3.3 and 3.4).  Values are ordered by IEEE totalOrder (-0 < +0);
+ * with lo and hi the elements of rank (T-1)/2 and T/2, the result is
+ * (lo + hi) * 0.5 in float32, which is lo when T is odd.  NaN input is a
+ * precondition violation.
+ *   stack : [T][N][N] float32 (only T and N of geom are used).
+ *   out   : [N][N] float32.
+ *   ws    : graphic_workspace_size(GRAPHIC_OP_MEDIAN) bytes (may be 0; then ws may be NULL).
+ */
+graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom,
+                              const float* stack, float* out,
+                              void* ws, size_t ws_bytes, graphic_stream stream);
+
+/*
+ * Classical ADI reduction (Sect. 3.3 and 3.4): S_i = shift(cube_i, dx_i, dy_i);
+ * PSF = median_i S_i; D_i = rotate(S_i - PSF, -parang_i); final = median_i D_i.
+ *   cube       : [T][N][N] float32 input (not modified).
+ *   dx, dy     : [T] float64 recentring shifts; parang_deg : [T] float64.
+ *   final_img  : [N][N] float32 output.
+ *   psf        : NULL or [N][N] float32, receives the median PSF.
+ *   residuals  : NULL or [T][N][N] float32, receives the derotated residuals D_i.
+ *   ws         : graphic_workspace_size(GRAPHIC_OP_ADI) bytes.
+ */
+graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
+                                  const float* cube, const double* dx, const double* dy,
+                                  const double* parang_deg, float* final_img,
+                                  float* psf, float* residuals,
+                                  void* ws, size_t ws_bytes, graphic_stream stream);
+
+/* Per-kernel timing with HIP events on the caller's stream (for benchmarks).
+ * When enabled, every library kernel launch is bracketed by events; the
+ * accumulated milliseconds and launch counts per kernel family are read with
+ * graphic_timing_read after the stream has been synchronised.  Names:
+ * "col_pass", "row_pass", "median", "aux". */
+graphic_status graphic_timing_enable(graphic_ctx ctx, int enable);
+graphic_status graphic_timing_read(graphic_ctx ctx, const char* family,
+                                   double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHIC_H */

@@ -255,7 +255,8 @@ def median_f32(stack):
     keys = np.sort(_total_order_key(st), axis=0)
     lo = _from_total_order_key(keys[(T - 1) // 2])
     hi = _from_total_order_key(keys[T // 2])
-    return ((lo + hi) * np.float32(0.5)).astype(np.float32)
+    with np.errstate(over="ignore"):       # |lo + hi| may round to inf in float32
+        return ((lo + hi) * np.float32(0.5)).astype(np.float32)
 
 
 def median_f64(stack):

@@ -1,0 +1,8 @@
+"""MI355X-native Fourier ADI hot path (GRAPHIC, arXiv:1510.04331).
+
+The computation lives in libgraphic.so (hand-written HIP for gfx950) behind the
+C ABI of include/graphic.h; this package only marshals torch tensors to it.
+"""
+
+from .ops import shift, rotate, median, adi_reduce, workspace_size, timing_enable, timing_read  # noqa: F401
+from ._abi import LIB_PATH, GraphicError  # noqa: F401

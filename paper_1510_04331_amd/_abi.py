@@ -1,0 +1,89 @@
+"""ctypes declarations of libgraphic.so (include/graphic.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Loading fails loudly when the library has not been built.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraphic.so")
+
+# status codes (graphic_status)
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM = range(6)
+OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN = range(4)
+
+# every symbol that include/graphic.h declares
+EXPORTS = (
+    "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
+    "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
+    "graphic_median", "graphic_adi_reduce", "graphic_timing_enable", "graphic_timing_read",
+)
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class GraphicError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s" % (where, status_string(status)))
+
+
+_lib = None
+
+
+def load():
+    """Load libgraphic.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgraphic.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    g = ctypes.POINTER(Geom)
+    st = ctypes.c_int
+    lib.graphic_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.graphic_create.restype = st
+    lib.graphic_destroy.argtypes = [vp]
+    lib.graphic_destroy.restype = None
+    lib.graphic_status_string.argtypes = [st]
+    lib.graphic_status_string.restype = ctypes.c_char_p
+    lib.graphic_version.argtypes = []
+    lib.graphic_version.restype = ctypes.c_char_p
+    lib.graphic_resolved_pad.argtypes = [g]
+    lib.graphic_resolved_pad.restype = i32
+    lib.graphic_workspace_size.argtypes = [vp, ctypes.c_int, g, ctypes.POINTER(sz)]
+    lib.graphic_workspace_size.restype = st
+    lib.graphic_shift.argtypes = [vp, g, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.graphic_shift.restype = st
+    lib.graphic_rotate.argtypes = [vp, g, vp, vp, vp, vp, vp, sz, vp]
+    lib.graphic_rotate.restype = st
+    lib.graphic_median.argtypes = [vp, g, vp, vp, vp, sz, vp]
+    lib.graphic_median.restype = st
+    lib.graphic_adi_reduce.argtypes = [vp, g, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.graphic_adi_reduce.restype = st
+    lib.graphic_timing_enable.argtypes = [vp, ctypes.c_int]
+    lib.graphic_timing_enable.restype = st
+    lib.graphic_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(i64)]
+    lib.graphic_timing_read.restype = st
+    _lib = lib
+    return lib
+
+
+def status_string(s):
+    try:
+        return load().graphic_status_string(int(s)).decode()
+    except Exception:  # pragma: no cover - only when the library is absent
+        return "status %d" % int(s)
+
+
+def check(status, where):
+    if status != OK:
+        raise GraphicError(status, where)

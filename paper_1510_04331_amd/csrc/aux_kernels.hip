@@ -1,0 +1,67 @@
+// Small per-frame kernels: rotation parameters and float64 flux sums.
+
+#include "internal.h"
+
+namespace graphic {
+
+namespace {
+
+// Three-shear factors of Sect. 3.4 for every frame: the rotation R(theta) is
+// S_x(-tan(theta/2)) S_y(sin theta) S_x(-tan(theta/2)).  For |theta| > 90
+// degrees an exact half-turn is taken out first (flip = 1) and theta is
+// reduced by 180 degrees toward zero, so that tan(theta/2) stays bounded.
+__global__ void rotation_params_kernel(const double* __restrict__ theta_deg, double sign, long long T,
+                                       int* __restrict__ flip, double* __restrict__ neg_tan_half,
+                                       double* __restrict__ sin_theta) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  double th = sign * theta_deg[i];
+  int fl = 0;
+  if (fabs(th) > 90.0) {
+    fl = 1;
+    th = th - copysign(180.0, th);
+  }
+  const double rad = th * (3.14159265358979323846 / 180.0);
+  flip[i] = fl;
+  neg_tan_half[i] = -tan(0.5 * rad);
+  sin_theta[i] = sin(rad);
+}
+
+// One block per frame; float64 partial sums combined in a fixed order, so the
+// result does not depend on scheduling.
+__global__ void __launch_bounds__(256) frame_sums_kernel(const float* __restrict__ frames, long long npix,
+                                                         double* __restrict__ flux, int slot) {
+  __shared__ double part[256];
+  const long long f = blockIdx.x;
+  const float* fr = frames + f * npix;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < npix; i += 256) acc += (double)fr[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flux[2 * f + slot] = part[0];
+}
+
+}  // namespace
+
+hipError_t launch_rotation_params(const double* theta_deg, double sign, long long T, int* flip,
+                                  double* neg_tan_half, double* sin_theta, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((T + 255) / 256);
+  hipLaunchKernelGGL(rotation_params_kernel, dim3(blocks), dim3(256), 0, s, theta_deg, sign, T, flip,
+                     neg_tan_half, sin_theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_sums(const float* frames, long long T, int N, double* flux, int slot,
+                             hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(frame_sums_kernel, dim3((unsigned)T), dim3(256), 0, s, frames, (long long)N * N, flux,
+                     slot);
+  return hipGetLastError();
+}
+
+}  // namespace graphic

@@ -1,0 +1,585 @@
+// C ABI of libgraphic: validation, workspace layout and pass orchestration.
+//
+// The operations are composed from three kernel families:
+//   line passes (line_pass.hip)  -- Fourier shifts of every line of a frame,
+//   the exact median (median.hip) and small per-frame kernels (aux_kernels.hip).
+//
+//   shift  (Sect. 3.3.1):  column pass (dy), row pass (dx), both in place on out.
+//   rotate (Sect. 3.4):    x-shear of every window row into a N x P scratch
+//                          frame, y-shear of every scratch column (in place),
+//                          x-shear of every window row into out.
+//   adi    (Sect. 3):      shift -> median PSF -> rotate(S - PSF, -parang)
+//                          with the subtraction fused into the first shear ->
+//                          median.
+
+#include "../../include/graphic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace graphic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxT_Median = 4096;
+constexpr size_t kDefaultChunkBytes = size_t(1) << 30;   // rotation scratch per chunk
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+struct TimingSlot {
+  std::string family;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct graphic_ctx_s {
+  int device = 0;
+  void* tables = nullptr;                 // one device allocation for every M
+  TwiddleTables tw[16] = {};              // indexed by log2(M)
+  bool timing = false;
+  std::vector<TimingSlot> pending;
+  struct Acc {
+    std::string family;
+    double ms = 0.0;
+    long long n = 0;
+  };
+  std::vector<Acc> acc;
+  size_t chunk_bytes = kDefaultChunkBytes;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Twiddle tables (float64 on the host, rounded once to float32)
+// ---------------------------------------------------------------------------
+void host_tables(int M, std::vector<float2>& fwd, std::vector<float2>& inv, std::vector<float2>& fold) {
+  const int lg = ilog2(M);
+  const int Ma = 1 << (lg / 2), Mb = M / Ma;
+  const double two_pi = 6.283185307179586476925286766559;
+  fwd.assign(M, float2{0, 0});
+  inv.assign(M, float2{0, 0});
+  fold.assign(2 * M, float2{0, 0});
+  for (int k2 = 0; k2 < Mb; ++k2)
+    for (int n1 = 0; n1 < Ma; ++n1) {
+      const long e = (long)n1 * k2 % M;
+      const double a = two_pi * (double)e / M;
+      fwd[k2 * Ma + n1] = float2{(float)std::cos(a), (float)-std::sin(a)};
+      inv[n1 * Mb + k2] = float2{(float)std::cos(a), (float)std::sin(a)};
+    }
+  for (int m = 0; m < M; ++m) {
+    fold[m] = float2{1.0f, 0.0f};
+    const double a = two_pi * (double)m / (2.0 * M);
+    fold[M + m] = float2{(float)std::cos(a), (float)-std::sin(a)};
+  }
+}
+
+graphic_status build_tables(graphic_ctx ctx) {
+  size_t total = 0;
+  for (int M = kMinM; M <= kMaxM; M *= 2) total += (size_t)4 * M * sizeof(float2);
+  std::vector<float2> host(total / sizeof(float2));
+  size_t off = 0;
+  std::vector<size_t> offs;
+  for (int M = kMinM; M <= kMaxM; M *= 2) {
+    std::vector<float2> f, i, fo;
+    host_tables(M, f, i, fo);
+    offs.push_back(off);
+    std::memcpy(&host[off], f.data(), M * sizeof(float2));
+    std::memcpy(&host[off + M], i.data(), M * sizeof(float2));
+    std::memcpy(&host[off + 2 * M], fo.data(), 2 * M * sizeof(float2));
+    off += 4 * M;
+  }
+  if (hipMalloc(&ctx->tables, total) != hipSuccess) return GRAPHIC_ERR_NOMEM;
+  if (hipMemcpy(ctx->tables, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return GRAPHIC_ERR_HIP;
+  int idx = 0;
+  for (int M = kMinM; M <= kMaxM; M *= 2, ++idx) {
+    const float2* base = static_cast<const float2*>(ctx->tables) + offs[idx];
+    TwiddleTables& t = ctx->tw[ilog2(M)];
+    t.fwd = base;
+    t.inv = base + M;
+    t.fold = base + 2 * M;
+  }
+  return GRAPHIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+graphic_status check_geom(const graphic_geom* g, int* P_out) {
+  if (!g) return GRAPHIC_ERR_ARG;
+  if (g->flags != 0) return GRAPHIC_ERR_ARG;
+  if (g->n_frames < 1) return GRAPHIC_ERR_ARG;
+  if (g->n < 4 || g->n > 4096 || (g->n % 2) != 0) return GRAPHIC_ERR_ARG;
+  int P = g->pad;
+  if (P == 0) {
+    P = 1;
+    while (P < 2 * g->n) P *= 2;
+  }
+  if (!is_pow2(P) || P < g->n || P < 2 * kMinM || P > 2 * kMaxM) return g->pad ? GRAPHIC_ERR_ARG : GRAPHIC_ERR_UNSUPPORTED;
+  *P_out = P;
+  return GRAPHIC_OK;
+}
+
+bool overlap_bad(const void* a, const void* b, size_t bytes) {
+  if (a == b) return false;
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+struct RotLayout {
+  size_t params = 0;      // flip (int), -tan(theta/2), sin(theta) per frame
+  size_t chunk_frames = 0;
+  size_t scratch = 0;     // chunk_frames * N * P floats
+  size_t total = 0;
+};
+
+RotLayout rot_layout(long long T, int N, int P, size_t chunk_bytes, size_t avail /*0 = choose*/) {
+  RotLayout L;
+  L.params = align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double));
+  const size_t per_frame = (size_t)N * P * sizeof(float);
+  size_t cf = avail ? (avail > L.params ? (avail - L.params) / per_frame : 0)
+                    : std::max<size_t>(1, chunk_bytes / per_frame);
+  if (cf > (size_t)T) cf = (size_t)T;
+  L.chunk_frames = cf;
+  L.scratch = align_up(cf * per_frame);
+  L.total = L.params + L.scratch;
+  return L;
+}
+
+size_t shift_ws(long long, int, int) { return 0; }
+
+size_t adi_ws(long long T, int N, int P, size_t chunk_bytes, bool have_residuals, bool have_psf) {
+  size_t s = 0;
+  if (!have_residuals) s += align_up((size_t)T * N * N * sizeof(float));
+  if (!have_psf) s += align_up((size_t)N * N * sizeof(float));
+  s += rot_layout(T, N, P, chunk_bytes, 0).total;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (with optional event timing)
+// ---------------------------------------------------------------------------
+struct Timer {
+  graphic_ctx ctx;
+  hipStream_t st;
+  const char* fam;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(graphic_ctx c, hipStream_t s, const char* f) : ctx(c), st(s), fam(f) {
+    if (ctx->timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, st);
+    }
+  }
+  void done() {
+    if (ctx->timing) {
+      hipEventRecord(b, st);
+      ctx->pending.push_back({fam, a, b});
+    }
+  }
+};
+
+graphic_status hip_ok(hipError_t e) { return e == hipSuccess ? GRAPHIC_OK : GRAPHIC_ERR_HIP; }
+
+graphic_status run_pass(graphic_ctx ctx, const LinePass& p, int kind, hipStream_t st) {
+  Timer t(ctx, st, kind == kRowPass ? "row_pass" : "col_pass");
+  hipError_t e = launch_line_pass(p, kind, 0, st);
+  t.done();
+  return hip_ok(e);
+}
+
+LinePass base_pass(graphic_ctx ctx, int P) {
+  LinePass p;
+  std::memset(&p, 0, sizeof(p));
+  p.P = P;
+  p.tw = ctx->tw[ilog2(P / 2)];
+  return p;
+}
+
+// Shift: column pass (content moves by dy along y) then row pass (dx along x).
+graphic_status do_shift(graphic_ctx ctx, long long T, int N, int P, const float* in, float* out,
+                        const double* dx, const double* dy, hipStream_t st) {
+  const int o = (P - N) / 2;
+  LinePass c = base_pass(ctx, P);
+  c.src = in;
+  c.dst = out;
+  c.src_fs = c.dst_fs = (long long)N * N;
+  c.src_ls = c.dst_ls = 1;
+  c.src_ps = c.dst_ps = N;
+  c.line_lo = o;
+  c.n_lines = N;
+  c.in_off = o;
+  c.in_len = N;
+  c.out_off = o;
+  c.out_len = N;
+  c.dst_line_lo = o;
+  c.mirror = 0;
+  c.n_jobs = N / 2;
+  c.n_frames = T;
+  c.sh0 = dy;
+  graphic_status s = run_pass(ctx, c, kColPass, st);
+  if (s != GRAPHIC_OK) return s;
+  LinePass r = c;
+  r.src = out;
+  r.src_ls = r.dst_ls = N;
+  r.src_ps = r.dst_ps = 1;
+  r.sh0 = dx;
+  return run_pass(ctx, r, kRowPass, st);
+}
+
+// Rotation of frames [0, T) of `src` into `dst` (may alias src), optionally
+// subtracting `sub` (N x N) from every source frame first.
+graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float* src, const float* sub,
+                         float* dst, const double* theta, double sign, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+  RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, ws_bytes);
+  if (L.chunk_frames < 1) return GRAPHIC_ERR_WORKSPACE;
+  char* w = static_cast<char*>(ws);
+  int* flip = reinterpret_cast<int*>(w);
+  double* ntan = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)));
+  double* sn = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)) + align_up((size_t)T * sizeof(double)));
+  float* scratch = reinterpret_cast<float*>(w + L.params);
+  {
+    Timer t(ctx, st, "aux");
+    hipError_t e = launch_rotation_params(theta, sign, T, flip, ntan, sn, st);
+    t.done();
+    if (e != hipSuccess) return GRAPHIC_ERR_HIP;
+  }
+  const int o = (P - N) / 2;
+  for (long long f0 = 0; f0 < T; f0 += (long long)L.chunk_frames) {
+    const long long nf = std::min<long long>((long long)L.chunk_frames, T - f0);
+    // x-shear 1: window rows -> all P columns of the scratch frame
+    LinePass a = base_pass(ctx, P);
+    a.src = src + f0 * (long long)N * N;
+    a.sub = sub;
+    a.dst = scratch;
+    a.src_fs = (long long)N * N;
+    a.dst_fs = (long long)N * P;
+    a.src_ls = N;
+    a.src_ps = 1;
+    a.sub_ls = N;
+    a.sub_ps = 1;
+    a.dst_ls = P;
+    a.dst_ps = 1;
+    a.line_lo = o;
+    a.n_lines = N;
+    a.in_off = o;
+    a.in_len = N;
+    a.out_off = 0;
+    a.out_len = P;
+    a.dst_line_lo = o;
+    a.mirror = 1;
+    a.n_jobs = N / 2 + 1;
+    a.n_frames = nf;
+    a.sh1 = ntan + f0;
+    a.flip = flip + f0;
+    a.flip_src_reverse = 1;
+    a.flip_lines = 1;
+    a.flip_in_off = 1;
+    graphic_status s = run_pass(ctx, a, kRowPass, st);
+    if (s != GRAPHIC_OK) return s;
+    // y-shear: every scratch column, window rows in and out (in place)
+    LinePass b = base_pass(ctx, P);
+    b.src = scratch;
+    b.dst = scratch;
+    b.src_fs = b.dst_fs = (long long)N * P;
+    b.src_ls = b.dst_ls = 1;
+    b.src_ps = b.dst_ps = P;
+    b.line_lo = 0;
+    b.n_lines = P;
+    b.in_off = o;
+    b.in_len = N;
+    b.out_off = o;
+    b.out_len = N;
+    b.dst_line_lo = 0;
+    b.mirror = 1;
+    b.n_jobs = P / 2 + 1;
+    b.n_frames = nf;
+    b.sh1 = sn + f0;
+    b.flip = flip + f0;
+    b.flip_in_off = 1;
+    s = run_pass(ctx, b, kColPass, st);
+    if (s != GRAPHIC_OK) return s;
+    // x-shear 2: window rows, all P columns in, window columns out
+    LinePass c = base_pass(ctx, P);
+    c.src = scratch;
+    c.dst = dst + f0 * (long long)N * N;
+    c.src_fs = (long long)N * P;
+    c.dst_fs = (long long)N * N;
+    c.src_ls = P;
+    c.src_ps = 1;
+    c.dst_ls = N;
+    c.dst_ps = 1;
+    c.line_lo = o;
+    c.n_lines = N;
+    c.in_off = 0;
+    c.in_len = P;
+    c.out_off = o;
+    c.out_len = N;
+    c.dst_line_lo = o;
+    c.mirror = 1;
+    c.n_jobs = N / 2 + 1;
+    c.n_frames = nf;
+    c.sh1 = ntan + f0;
+    s = run_pass(ctx, c, kRowPass, st);
+    if (s != GRAPHIC_OK) return s;
+  }
+  return GRAPHIC_OK;
+}
+
+graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, hipStream_t st) {
+  Timer t(ctx, st, "median");
+  hipError_t e = launch_median(stack, T, (long long)N * N, out, st);
+  t.done();
+  return hip_ok(e);
+}
+
+graphic_status do_sums(graphic_ctx ctx, long long T, int N, const float* frames, double* flux, int slot,
+                       hipStream_t st) {
+  Timer t(ctx, st, "aux");
+  hipError_t e = launch_frame_sums(frames, T, N, flux, slot, st);
+  t.done();
+  return hip_ok(e);
+}
+
+bool ws_ok(const void* ws, size_t have, size_t need) {
+  if (need == 0) return true;
+  if (!ws || have < need) return false;
+  return (reinterpret_cast<uintptr_t>(ws) % kAlign) == 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Public entry points
+// ===========================================================================
+extern "C" {
+
+const char* graphic_status_string(graphic_status s) {
+  switch (s) {
+    case GRAPHIC_OK: return "GRAPHIC_OK";
+    case GRAPHIC_ERR_ARG: return "GRAPHIC_ERR_ARG: invalid argument";
+    case GRAPHIC_ERR_UNSUPPORTED: return "GRAPHIC_ERR_UNSUPPORTED: unsupported geometry";
+    case GRAPHIC_ERR_WORKSPACE: return "GRAPHIC_ERR_WORKSPACE: workspace missing, too small or misaligned";
+    case GRAPHIC_ERR_HIP: return "GRAPHIC_ERR_HIP: HIP runtime error";
+    case GRAPHIC_ERR_NOMEM: return "GRAPHIC_ERR_NOMEM: out of device memory";
+  }
+  return "GRAPHIC: unknown status";
+}
+
+const char* graphic_version(void) { return "graphic-mi355x 0.1 (gfx950)"; }
+
+int32_t graphic_resolved_pad(const graphic_geom* geom) {
+  int P = 0;
+  return check_geom(geom, &P) == GRAPHIC_OK ? P : -1;
+}
+
+graphic_status graphic_create(graphic_ctx* out, int hip_device) {
+  if (!out) return GRAPHIC_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return GRAPHIC_ERR_HIP;
+  if (hipSetDevice(hip_device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  graphic_ctx c = new graphic_ctx_s();
+  c->device = hip_device;
+  if (const char* env = std::getenv("GRAPHIC_ROTATE_CHUNK_MB")) {
+    long v = std::atol(env);
+    if (v > 0) c->chunk_bytes = (size_t)v << 20;
+  }
+  graphic_status s = build_tables(c);
+  if (s != GRAPHIC_OK) {
+    graphic_destroy(c);
+    return s;
+  }
+  *out = c;
+  return GRAPHIC_OK;
+}
+
+void graphic_destroy(graphic_ctx ctx) {
+  if (!ctx) return;
+  for (auto& p : ctx->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  if (ctx->tables) hipFree(ctx->tables);
+  delete ctx;
+}
+
+graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geom* geom, size_t* bytes) {
+  if (!bytes) return GRAPHIC_ERR_ARG;
+  int P = 0;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  const size_t chunk = ctx ? ctx->chunk_bytes : kDefaultChunkBytes;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  switch (op) {
+    case GRAPHIC_OP_SHIFT: *bytes = shift_ws(T, N, P); return GRAPHIC_OK;
+    case GRAPHIC_OP_ROTATE: *bytes = rot_layout(T, N, P, chunk, 0).total; return GRAPHIC_OK;
+    case GRAPHIC_OP_ADI: *bytes = adi_ws(T, N, P, chunk, false, false); return GRAPHIC_OK;
+    case GRAPHIC_OP_MEDIAN: *bytes = 0; return T > kMaxT_Median ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+    default: return GRAPHIC_ERR_ARG;
+  }
+}
+
+graphic_status graphic_shift(graphic_ctx ctx, const graphic_geom* geom, const float* in, float* out,
+                             const double* dx, const double* dy, double* flux, void* ws, size_t ws_bytes,
+                             graphic_stream stream) {
+  int P = 0;
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (!in || !out || !dx || !dy) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t bytes = (size_t)T * N * N * sizeof(float);
+  if (overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, shift_ws(T, N, P))) return GRAPHIC_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
+  if ((s = do_shift(ctx, T, N, P, in, out, dx, dy, st)) != GRAPHIC_OK) return s;
+  if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom, const float* in, float* out,
+                              const double* theta_deg, double* flux, void* ws, size_t ws_bytes,
+                              graphic_stream stream) {
+  int P = 0;
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (!in || !out || !theta_deg) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t bytes = (size_t)T * N * N * sizeof(float);
+  if (overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
+  RotLayout need = rot_layout(T, N, P, ctx->chunk_bytes, 0);
+  const size_t minimum = need.params + align_up((size_t)N * P * sizeof(float));
+  if (!ws_ok(ws, ws_bytes, minimum)) return GRAPHIC_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
+  if ((s = do_rotate(ctx, T, N, P, in, nullptr, out, theta_deg, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
+  if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const float* stack, float* out,
+                              void* ws, size_t ws_bytes, graphic_stream stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!ctx || !geom || !stack || !out) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames < 1 || geom->n < 1 || geom->flags != 0) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  if (overlap_bad(stack, out, (size_t)N * N * sizeof(float)) ||
+      (out >= stack && out < stack + (size_t)T * N * N))
+    return GRAPHIC_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  return do_median(ctx, T, N, stack, out, static_cast<hipStream_t>(stream));
+}
+
+graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, const float* cube, const double* dx,
+                                  const double* dy, const double* parang_deg, float* final_img, float* psf,
+                                  float* residuals, void* ws, size_t ws_bytes, graphic_stream stream) {
+  int P = 0;
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (!cube || !dx || !dy || !parang_deg || !final_img) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  if (T > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+  const size_t cube_bytes = (size_t)T * N * N * sizeof(float);
+  const size_t img_bytes = (size_t)N * N * sizeof(float);
+  if (residuals && overlap_bad(cube, residuals, cube_bytes)) return GRAPHIC_ERR_ARG;
+  if (residuals && residuals == cube) return GRAPHIC_ERR_ARG;
+  if (overlap_bad(cube, final_img, img_bytes) ||
+      ((const char*)final_img >= (const char*)cube && (const char*)final_img < (const char*)cube + cube_bytes))
+    return GRAPHIC_ERR_ARG;
+  if (psf && psf == final_img) return GRAPHIC_ERR_ARG;
+  // workspace: [stack of shifted frames unless residuals given][psf unless given][rotation]
+  const size_t stack_b = residuals ? 0 : align_up(cube_bytes);
+  const size_t psf_b = psf ? 0 : align_up(img_bytes);
+  const RotLayout L0 = rot_layout(T, N, P, ctx->chunk_bytes, 0);
+  const size_t minimum = stack_b + psf_b + L0.params + align_up((size_t)N * P * sizeof(float));
+  if (!ws_ok(ws, ws_bytes, minimum)) return GRAPHIC_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  char* w = static_cast<char*>(ws);
+  float* stack = residuals ? residuals : reinterpret_cast<float*>(w);
+  float* psf_buf = psf ? psf : reinterpret_cast<float*>(w + stack_b);
+  void* rot_ws = w + stack_b + psf_b;
+  const size_t rot_bytes = ws_bytes - stack_b - psf_b;
+  if ((s = do_shift(ctx, T, N, P, cube, stack, dx, dy, st)) != GRAPHIC_OK) return s;
+  if ((s = do_median(ctx, T, N, stack, psf_buf, st)) != GRAPHIC_OK) return s;
+  if ((s = do_rotate(ctx, T, N, P, stack, psf_buf, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
+    return s;
+  return do_median(ctx, T, N, stack, final_img, st);
+}
+
+graphic_status graphic_timing_enable(graphic_ctx ctx, int enable) {
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  for (auto& p : ctx->pending) {
+    hipEventSynchronize(p.stop);
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->pending.clear();
+  ctx->acc.clear();
+  ctx->timing = enable != 0;
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_timing_read(graphic_ctx ctx, const char* family, double* total_ms, int64_t* launches) {
+  if (!ctx || !family || !total_ms || !launches) return GRAPHIC_ERR_ARG;
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.stop) != hipSuccess) return GRAPHIC_ERR_HIP;
+    hipEventElapsedTime(&ms, p.start, p.stop);
+    bool found = false;
+    for (auto& a : ctx->acc)
+      if (a.family == p.family) {
+        a.ms += ms;
+        a.n += 1;
+        found = true;
+      }
+    if (!found) ctx->acc.push_back({p.family, (double)ms, 1});
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  ctx->pending.clear();
+  *total_ms = 0.0;
+  *launches = 0;
+  for (auto& a : ctx->acc)
+    if (a.family == family) {
+      *total_ms = a.ms;
+      *launches = a.n;
+    }
+  return GRAPHIC_OK;
+}
+
+}  // extern "C"

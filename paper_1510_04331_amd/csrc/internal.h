@@ -1,0 +1,75 @@
+// Internal declarations shared by the C ABI (graphic.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace graphic {
+
+constexpr int kMinM = 8;      // smallest half working size (P = 16)
+constexpr int kMaxM = 2048;   // largest half working size (P = 4096)
+
+// Twiddle tables of one half size M = P/2, in device memory.
+//   fwd[k2*Ma + n1]  = exp(-2 pi i n1 k2 / M)          (four-step, forward)
+//   inv[n1*Mb + k2]  = exp(+2 pi i n1 k2 / M)          (four-step, inverse)
+//   fold[h*M + m]    = 1 (h = 0) or exp(-2 pi i m / P) (h = 1)
+struct TwiddleTables {
+  const float2* fwd;
+  const float2* inv;
+  const float2* fold;
+};
+
+// One pass of one-dimensional Fourier shifts over the lines of a stack of
+// 2-D arrays.  Coordinates along and across the lines are those of the
+// zero-padded P x P frame; the mapping to array indices is described by the
+// offsets below.  See line_pass.hip for the algorithm.
+struct LinePass {
+  // memory: element (frame f, line li, position pi) at base + f*fs + li*ls + pi*ps
+  const float* src;
+  float* dst;
+  const float* sub;       // nullable N x N frame subtracted from every source value
+  long long src_fs, dst_fs;
+  int src_ls, src_ps, dst_ls, dst_ps, sub_ls, sub_ps;
+
+  int P;                  // working size
+  int line_lo;            // first line (padded coordinate) of the line set
+  int n_lines;            // number of lines in the set (source and destination)
+  int in_off, in_len;     // source support along the line: [in_off, in_off+in_len)
+  int out_off, out_len;   // destination window along the line
+  int dst_line_lo;        // destination array line index = line - dst_line_lo
+
+  int mirror;             // 0: pair lines (l, l+1) with one shift; 1: pair (c-d, c+d)
+  int n_jobs;             // jobs (line pairs) per frame
+  long long n_frames;
+
+  // shift of line l in frame f: sh0[f] + sh1[f] * (l - P/2)   (either may be null)
+  const double* sh0;
+  const double* sh1;
+
+  // per-frame half-turn flag (nullable) and where it acts
+  const int* flip;
+  int flip_src_reverse;   // source array read reversed along and across lines
+  int flip_lines;         // line set and destination lines start one later
+  int flip_in_off;        // source support starts one later
+
+  TwiddleTables tw;
+};
+
+enum PassKind { kRowPass = 0, kColPass = 1 };
+
+hipError_t launch_line_pass(const LinePass& p, int kind, int jobs_per_block, hipStream_t s);
+
+// Per-frame rotation parameters from angles: flip (|theta| > 90), -tan(theta'/2), sin(theta').
+hipError_t launch_rotation_params(const double* theta_deg, double sign, long long T,
+                                  int* flip, double* neg_tan_half, double* sin_theta,
+                                  hipStream_t s);
+
+// Exact per-pixel median of a [T][npix] stack -> [npix].
+hipError_t launch_median(const float* stack, long long T, long long npix, float* out, hipStream_t s);
+
+// Per-frame float64 sums of [T][N][N] frames into flux[2*t + slot].
+hipError_t launch_frame_sums(const float* frames, long long T, int N, double* flux, int slot,
+                             hipStream_t s);
+
+}  // namespace graphic

@@ -1,0 +1,160 @@
+// Exact per-pixel median of a float32 stack (gfx950).
+//
+// The classical ADI reference PSF is the per-pixel median of the recentred
+// frames (Sect. 3.3), and the derotated residuals are merged with a per-pixel
+// median (Sect. 3.4).  The result is exact: values are ordered by IEEE
+// totalOrder through the usual order-preserving uint32 key, lo is the element
+// of rank (T-1)/2, hi the element of rank T/2, and the median is
+// (lo + hi) * 0.5 in float32.
+//
+// Layout: a block of 1024 threads owns 16 consecutive pixels and all T values
+// of each (16 waves; lanes = 16 pixels x 4 frame groups, so every load reads
+// 64 contiguous bytes of one frame).  Thread (pixel, g) keeps the keys of
+// frames g, g+64, g+128, ... in registers, so the stack is read from HBM once.
+// The rank-(T-1)/2 key is found by a most-significant-digit-first radix select
+// with four 8-bit digits; each digit builds a 256-bin histogram per pixel in
+// LDS and one wave per pixel scans it.  hi is lo itself when at least T/2+1
+// keys are <= lo, otherwise the smallest key above lo.
+
+#include "internal.h"
+
+namespace graphic {
+
+namespace {
+
+constexpr int kPix = 16;          // pixels per block
+constexpr int kGroups = 64;       // frame groups (threads) per pixel
+constexpr int kThreads = kPix * kGroups;
+constexpr int kBins = 256;
+constexpr int kHistPitch = kBins + 1;   // +1 word: pixels land on distinct banks
+
+__device__ __forceinline__ unsigned key_of(float v) {
+  unsigned b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float val_of(unsigned k) {
+  unsigned b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(b);
+}
+
+template <int VPT>
+__global__ void __launch_bounds__(kThreads) median_kernel(const float* __restrict__ stack, long long T,
+                                                          long long npix, float* __restrict__ out) {
+  __shared__ unsigned hist[kPix * kHistPitch];
+  __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int px = lane & (kPix - 1);
+  const int g = (lane >> 4) + 4 * wave;          // frame group 0..63
+  const long long pix = (long long)blockIdx.x * kPix + px;
+  const bool pix_ok = pix < npix;
+
+  unsigned key[VPT];
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const long long t = g + (long long)kGroups * i;
+    key[i] = 0xFFFFFFFFu;   // padding sorts after every real (non-NaN) value
+    if (pix_ok && t < T) key[i] = key_of(stack[t * npix + pix]);
+  }
+
+  const unsigned k_lo = (unsigned)((T - 1) / 2);
+  if (tid < kPix) {
+    sel_prefix[tid] = 0u;
+    sel_rank[tid] = k_lo;
+  }
+
+  unsigned prefix = 0u, mask = 0u;
+#pragma unroll 1
+  for (int d = 3; d >= 0; --d) {
+    for (int i = tid; i < kPix * kHistPitch; i += kThreads) hist[i] = 0u;
+    __syncthreads();
+    prefix = sel_prefix[px];
+    const int sh = 8 * d;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      if ((key[i] & mask) == prefix) atomicAdd(&hist[px * kHistPitch + ((key[i] >> sh) & 0xFFu)], 1u);
+    }
+    __syncthreads();
+    // wave w scans the histogram of pixel w: lane l holds bins l, l+64, l+128, l+192
+    {
+      const int w = wave;
+      const unsigned k = sel_rank[w];
+      unsigned carry = 0u;
+      int found_bin = -1;
+      unsigned below = 0u, inbin = 0u;
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) {
+        const unsigned x = hist[w * kHistPitch + blk * 64 + lane];
+        unsigned incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const unsigned y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
+        const unsigned tot = __shfl(incl, 63, 64);
+        const unsigned long long hit = __ballot(carry + incl > k);
+        if (found_bin < 0 && hit != 0ull) {
+          const int l0 = __ffsll((long long)hit) - 1;
+          found_bin = blk * 64 + l0;
+          const unsigned incl0 = __shfl(incl, l0, 64);
+          const unsigned x0 = __shfl(x, l0, 64);
+          below = carry + incl0 - x0;
+          inbin = x0;
+        }
+        carry += tot;
+      }
+      if (lane == 0) {
+        sel_prefix[w] = sel_prefix[w] | ((unsigned)found_bin << sh);
+        sel_rank[w] = k - below;
+        sel_cnt[w] = inbin;
+        sel_min[w] = 0xFFFFFFFFu;
+      }
+    }
+    mask |= 0xFFu << sh;
+    __syncthreads();
+  }
+
+  // After the last digit, sel_rank is lo's rank among the keys equal to lo and
+  // sel_cnt is how many keys equal lo; rank T/2 still hits lo iff it falls
+  // inside that run, otherwise hi is the smallest key above lo.
+  const unsigned lo_key = sel_prefix[px];
+  unsigned local_min = 0xFFFFFFFFu;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i)
+    if (key[i] > lo_key && key[i] < local_min) local_min = key[i];
+  atomicMin(&sel_min[px], local_min);
+  __syncthreads();
+
+  if (pix_ok && g == 0) {
+    const unsigned step = (unsigned)(T / 2) - k_lo;      // 0 (odd T) or 1
+    const float lo = val_of(lo_key);
+    const float hi = (sel_rank[px] + step < sel_cnt[px]) ? lo : val_of(sel_min[px]);
+    out[pix] = (lo + hi) * 0.5f;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_median(const float* stack, long long T, long long npix, float* out, hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  const long long vpt = (T + kGroups - 1) / kGroups;
+  const unsigned blocks = (unsigned)((npix + kPix - 1) / kPix);
+#define GRAPHIC_MEDIAN_CASE(V)                                                                     \
+  if (vpt <= V) {                                                                                 \
+    hipLaunchKernelGGL((median_kernel<V>), dim3(blocks), dim3(kThreads), 0, s, stack, T, npix, out); \
+    return hipGetLastError();                                                                     \
+  }
+  GRAPHIC_MEDIAN_CASE(1)
+  GRAPHIC_MEDIAN_CASE(2)
+  GRAPHIC_MEDIAN_CASE(4)
+  GRAPHIC_MEDIAN_CASE(8)
+  GRAPHIC_MEDIAN_CASE(16)
+  GRAPHIC_MEDIAN_CASE(32)
+  GRAPHIC_MEDIAN_CASE(64)
+#undef GRAPHIC_MEDIAN_CASE
+  return hipErrorInvalidValue;   // T > 4096: rejected on the host before launch
+}
+
+}  // namespace graphic

@@ -1,0 +1,157 @@
+"""Python entry points over the C ABI (torch tensors in, torch tensors out).
+
+PyTorch supplies device memory and the current stream; the computation is the
+HIP library's.  Names follow the C ABI: shift, rotate, median, adi_reduce.
+"""
+
+import ctypes
+
+from . import _abi
+
+_contexts = {}
+
+
+def context(device_index):
+    """The library context of one HIP device (created on first use)."""
+    ctx = _contexts.get(device_index)
+    if ctx is None:
+        lib = _abi.load()
+        h = ctypes.c_void_p()
+        _abi.check(lib.graphic_create(ctypes.byref(h), int(device_index)), "graphic_create")
+        ctx = h
+        _contexts[device_index] = ctx
+    return ctx
+
+
+def _geom(T, N, pad):
+    return _abi.Geom(int(T), int(N), int(pad or 0), 0)
+
+
+def _stream(dev):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _check_cube(x, name="cube"):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if x.dtype != torch.float32 or x.dim() != 3 or x.shape[1] != x.shape[2] or not x.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 [T, N, N] tensor" % name)
+    return x.shape[0], x.shape[1]
+
+
+def _f64(v, T, dev, name):
+    import torch
+    t = torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous()
+    if t.shape != (T,):
+        raise ValueError("%s must have shape [T]" % name)
+    return t
+
+
+def workspace_size(op, T, N, pad=None, device_index=0):
+    lib = _abi.load()
+    out = ctypes.c_size_t()
+    g = _geom(T, N, pad)
+    _abi.check(lib.graphic_workspace_size(context(device_index), op, ctypes.byref(g), ctypes.byref(out)),
+               "graphic_workspace_size")
+    return out.value
+
+
+def _workspace(op, T, N, pad, dev):
+    import torch
+    n = workspace_size(op, T, N, pad, dev.index or 0)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=dev), n
+
+
+def shift(cube, dx, dy, pad=None, out=None, flux=False):
+    """Fourier shift of every frame by (dx[i], dy[i]) pixels (content moves
+    toward +x, +y).  Returns ``out`` (and a [T, 2] float64 flux tensor)."""
+    import torch
+    T, N = _check_cube(cube)
+    dev = cube.device
+    dx, dy = _f64(dx, T, dev, "dx"), _f64(dy, T, dev, "dy")
+    out = torch.empty_like(cube) if out is None else out
+    _check_cube(out, "out")
+    fl = torch.empty((T, 2), dtype=torch.float64, device=dev) if flux else None
+    ws, n = _workspace(_abi.OP_SHIFT, T, N, pad, dev)
+    g = _geom(T, N, pad)
+    lib = _abi.load()
+    _abi.check(lib.graphic_shift(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(out), _ptr(dx),
+                                 _ptr(dy), _ptr(fl), _ptr(ws), n, _stream(dev)), "graphic_shift")
+    return (out, fl) if flux else out
+
+
+def rotate(cube, theta_deg, pad=None, out=None, flux=False):
+    """Three-shear Fourier rotation of every frame by theta_deg[i] degrees
+    (counter-clockwise, centre at pixel (N/2, N/2))."""
+    import torch
+    T, N = _check_cube(cube)
+    dev = cube.device
+    th = _f64(theta_deg, T, dev, "theta_deg")
+    out = torch.empty_like(cube) if out is None else out
+    _check_cube(out, "out")
+    fl = torch.empty((T, 2), dtype=torch.float64, device=dev) if flux else None
+    ws, n = _workspace(_abi.OP_ROTATE, T, N, pad, dev)
+    g = _geom(T, N, pad)
+    lib = _abi.load()
+    _abi.check(lib.graphic_rotate(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(out), _ptr(th),
+                                  _ptr(fl), _ptr(ws), n, _stream(dev)), "graphic_rotate")
+    return (out, fl) if flux else out
+
+
+def median(stack, out=None):
+    """Exact per-pixel float32 median over axis 0 of a [T, N, N] stack."""
+    import torch
+    T, N = _check_cube(stack, "stack")
+    out = torch.empty((N, N), dtype=torch.float32, device=stack.device) if out is None else out
+    g = _geom(T, N, 0)
+    lib = _abi.load()
+    _abi.check(lib.graphic_median(context(stack.device.index or 0), ctypes.byref(g), _ptr(stack), _ptr(out),
+                                  None, 0, _stream(stack.device)), "graphic_median")
+    return out
+
+
+def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, workspace=None):
+    """Classical ADI: recentre, median PSF, subtract, derotate by -parang,
+    median combine.  Returns the final image, plus the PSF and the derotated
+    residual cube when asked."""
+    import torch
+    T, N = _check_cube(cube)
+    dev = cube.device
+    dx, dy = _f64(dx, T, dev, "dx"), _f64(dy, T, dev, "dy")
+    pa = _f64(parang_deg, T, dev, "parang_deg")
+    final = torch.empty((N, N), dtype=torch.float32, device=dev)
+    psf_t = torch.empty((N, N), dtype=torch.float32, device=dev) if psf else None
+    res_t = torch.empty_like(cube) if residuals else None
+    if workspace is None:
+        ws, n = _workspace(_abi.OP_ADI, T, N, pad, dev)
+    else:
+        ws, n = workspace, workspace.numel()
+    g = _geom(T, N, pad)
+    lib = _abi.load()
+    _abi.check(lib.graphic_adi_reduce(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(dx), _ptr(dy),
+                                      _ptr(pa), _ptr(final), _ptr(psf_t), _ptr(res_t), _ptr(ws), n,
+                                      _stream(dev)), "graphic_adi_reduce")
+    out = [final]
+    if psf:
+        out.append(psf_t)
+    if residuals:
+        out.append(res_t)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def timing_enable(enable=True, device_index=0):
+    _abi.check(_abi.load().graphic_timing_enable(context(device_index), int(bool(enable))), "graphic_timing_enable")
+
+
+def timing_read(family, device_index=0):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _abi.check(_abi.load().graphic_timing_read(context(device_index), family.encode(), ctypes.byref(ms),
+                                               ctypes.byref(n)), "graphic_timing_read")
+    return ms.value, n.value

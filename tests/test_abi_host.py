@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and its host-only queries validate geometry (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1510_04331_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "graphic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(graphic_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _abi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_abi.EXPORTS)
+
+
+def test_status_strings_and_version(lib):
+    for s in range(6):
+        assert lib.graphic_status_string(s).startswith(b"GRAPHIC")
+    assert b"gfx950" in lib.graphic_version()
+
+
+@pytest.mark.parametrize("n,pad,expect", [
+    (128, 0, 256), (100, 0, 256), (6, 0, 16), (64, 64, 64), (48, 256, 256),
+    (1024, 0, 2048), (2048, 0, 4096),
+    (7, 0, -1), (0, 0, -1), (4, 8, -1), (64, 96, -1), (64, 32, -1), (4096, 0, -1), (64, 8192, -1),
+])
+def test_resolved_pad(lib, n, pad, expect):
+    g = _abi.Geom(3, n, pad, 0)
+    assert lib.graphic_resolved_pad(ctypes.byref(g)) == expect
+
+
+def test_workspace_sizes(lib):
+    sz = ctypes.c_size_t()
+    g = _abi.Geom(16, 128, 0, 0)
+    assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value == 0
+    assert lib.graphic_workspace_size(None, _abi.OP_ROTATE, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 16 * 128 * 256 * 4
+    assert lib.graphic_workspace_size(None, _abi.OP_ADI, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 16 * 128 * 128 * 4 + 16 * 128 * 256 * 4
+    g_big = _abi.Geom(5000, 64, 0, 0)
+    assert lib.graphic_workspace_size(None, _abi.OP_MEDIAN, ctypes.byref(g_big), ctypes.byref(sz)) == \
+        _abi.ERR_UNSUPPORTED
+    bad = _abi.Geom(16, 7, 0, 0)
+    assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(bad), ctypes.byref(sz)) == _abi.ERR_ARG
+    flags = _abi.Geom(16, 8, 0, 1)
+    assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(flags), ctypes.byref(sz)) == _abi.ERR_ARG
+    assert lib.graphic_workspace_size(None, 99, ctypes.byref(g), ctypes.byref(sz)) == _abi.ERR_ARG
+
+
+def test_entry_points_reject_null_context(lib):
+    g = _abi.Geom(1, 8, 0, 0)
+    assert lib.graphic_shift(None, ctypes.byref(g), None, None, None, None, None, None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_rotate(None, ctypes.byref(g), None, None, None, None, None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_adi_reduce(None, ctypes.byref(g), None, None, None, None, None, None, None, None, 0,
+                                  None) == _abi.ERR_ARG
+    assert lib.graphic_median(None, ctypes.byref(g), None, None, None, 0, None) == _abi.ERR_ARG

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (per result): relative L2 error <= 1e-5 per frame for shift and
+rotate, flux error |sum_gpu - sum_oracle| / sum|x_in| <= 1e-6, the median
+bit-exact on identical float32 input, and for the end-to-end reduction
+||final_gpu - final_oracle|| / ||PSF_oracle|| <= 1e-5.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+FLUX = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd as G  # noqa: F401  (fails loudly if the library is missing)
+    return torch, torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _cube(T, N, seed, blobs=True):
+    rng = np.random.default_rng(seed)
+    c = rng.normal(0.0, 5.0, size=(T, N, N))
+    if blobs:
+        yy, xx = np.mgrid[0:N, 0:N]
+        for t in range(T):
+            x0, y0 = rng.uniform(N * 0.3, N * 0.7, size=2)
+            c[t] += 1e3 * np.exp(-((xx - x0) ** 2 + (yy - y0) ** 2) / (2 * 2.0 ** 2))
+    return c.astype(np.float32)
+
+
+SHIFT_CASES = [
+    # (T, N, pad) -- tiles of every size, ragged frame counts, P = N, P > 2N
+    (3, 8, 0), (5, 6, 0), (7, 16, 0), (4, 30, 0), (3, 64, 64), (2, 48, 256), (5, 100, 0),
+    (16, 128, 0), (3, 200, 512), (2, 256, 0), (3, 512, 0), (2, 1024, 0),
+]
+
+
+@pytest.mark.parametrize("T,N,pad", SHIFT_CASES)
+def test_shift_parity(torch_dev, T, N, pad):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("shift parity T=%d N=%d pad=%d" % (T, N, pad), flush=True)
+    cube = _cube(T, N, seed=N + T)
+    rng = np.random.default_rng(N)
+    dx = rng.uniform(-1, 1, T)
+    dy = rng.uniform(-1, 1, T)
+    dx[0], dy[0] = 3.5, 2.7              # the paper's double-shift example
+    if T > 2:
+        dx[1], dy[1] = -0.3 * N, 0.21 * N  # large shifts exercise the phase reduction
+    x = torch.from_numpy(cube).to(dev)
+    out, fl = G.shift(x, dx, dy, pad=pad or None, flux=True)
+    got = out.cpu().numpy()
+    flh = fl.cpu().numpy()
+    P = pad or O.padded_size(N)
+    for t in range(T):
+        ref = O.shift(cube[t], dx[t], dy[t], P=P)
+        assert _rel(got[t], ref) <= REL_L2, (t, _rel(got[t], ref))
+        assert abs(flh[t, 0] - cube[t].astype(np.float64).sum()) <= 1e-9 * np.abs(cube[t]).sum()
+        assert abs(flh[t, 1] - got[t].astype(np.float64).sum()) <= 1e-9 * np.abs(cube[t]).sum()
+        assert abs(got[t].astype(np.float64).sum() - ref.sum()) <= FLUX * np.abs(cube[t]).sum()
+
+
+ROT_ANGLES = [0.0, 11.3, -30.0, 45.0, 90.0, -90.0, 135.0, -170.0, 180.0, 0.7]
+
+
+@pytest.mark.parametrize("N,pad", [(8, 0), (6, 0), (64, 0), (64, 64), (40, 256), (128, 0)])
+def test_rotate_parity(torch_dev, N, pad):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("rotate parity N=%d pad=%d" % (N, pad), flush=True)
+    T = len(ROT_ANGLES)
+    cube = _cube(T, N, seed=3 * N)
+    x = torch.from_numpy(cube).to(dev)
+    out, fl = G.rotate(x, ROT_ANGLES, pad=pad or None, flux=True)
+    got = out.cpu().numpy()
+    P = pad or O.padded_size(N)
+    for t in range(T):
+        ref = O.rotate(cube[t], ROT_ANGLES[t], P=P)
+        assert _rel(got[t], ref) <= REL_L2, (ROT_ANGLES[t], _rel(got[t], ref))
+        assert abs(got[t].astype(np.float64).sum() - ref.sum()) <= FLUX * np.abs(cube[t]).sum()
+
+
+@pytest.mark.parametrize("T,N", [(3, 512), (2, 1024)])
+def test_rotate_parity_large(torch_dev, T, N):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("rotate parity large T=%d N=%d" % (T, N), flush=True)
+    cube = _cube(T, N, seed=N)
+    ang = [-30.0, 17.25, 29.9][:T]
+    out = G.rotate(torch.from_numpy(cube).to(dev), ang).cpu().numpy()
+    for t in range(T):
+        ref = O.rotate(cube[t], ang[t])
+        assert _rel(out[t], ref) <= REL_L2
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 16, 17, 64, 65, 100, 1024, 4096])
+def test_median_bit_exact(torch_dev, T):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("median T=%d" % T, flush=True)
+    N = 24 if T < 1024 else 8
+    rng = np.random.default_rng(T)
+    st = rng.normal(size=(T, N, N)).astype(np.float32)
+    st[:, 0, :] = np.round(st[:, 0, :] * 2) / 2            # ties
+    st[:, 1, 0] = 0.0
+    st[: T // 2, 1, 0] = -0.0                             # signed zeros
+    st[:, 1, 1] = rng.choice(np.array([1.0, 1.0000001, -3e38, 3e38], np.float32), size=T)
+    got = G.median(torch.from_numpy(st).to(dev)).cpu().numpy()
+    ref = O.median_f32(st)
+    assert got.tobytes() == ref.tobytes()
+
+
+def test_adi_reduce_parity_config1(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("adi config 1", flush=True)
+    p = synth.make_params(1)
+    cube = synth.render_host(p)
+    x = torch.from_numpy(cube).to(dev)
+    fin, psf, res = G.adi_reduce(x, p.dx, p.dy, p.parang, psf=True, residuals=True)
+    ref = O.adi_reduce(cube, p.dx, p.dy, p.parang)
+    scale = np.linalg.norm(ref["psf"])
+    assert np.linalg.norm(psf.cpu().numpy() - ref["psf"]) / scale <= REL_L2
+    assert np.linalg.norm(fin.cpu().numpy() - ref["final"]) / scale <= REL_L2
+    r = res.cpu().numpy()
+    for t in range(p.T):
+        assert np.linalg.norm(r[t] - ref["derotated"][t]) / scale <= REL_L2
+
+
+def test_adi_identical_frames_zero(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    f = _cube(1, 32, seed=1)[0]
+    x = torch.from_numpy(np.stack([f] * 5)).to(dev)
+    fin = G.adi_reduce(x, [0.3] * 5, [-0.2] * 5, [0.0] * 5).cpu().numpy()
+    assert np.all(fin == 0.0)
+
+
+def test_in_place_and_determinism(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    cube = _cube(4, 64, seed=9)
+    x = torch.from_numpy(cube).to(dev)
+    a = G.shift(x, [0.3, -0.7, 1.1, 0.0], [0.2, 0.5, -1.0, 2.0])
+    b = G.shift(x, [0.3, -0.7, 1.1, 0.0], [0.2, 0.5, -1.0, 2.0])
+    assert torch.equal(a, b)
+    y = x.clone()
+    G.shift(y, [0.3, -0.7, 1.1, 0.0], [0.2, 0.5, -1.0, 2.0], out=y)
+    assert torch.equal(y, a)
+    r1 = G.rotate(x, [10.0, -20.0, 100.0, 0.0])
+    z = x.clone()
+    G.rotate(z, [10.0, -20.0, 100.0, 0.0], out=z)
+    assert torch.equal(z, r1)
+
+
+def test_errors_launch_nothing(torch_dev):
+    torch, dev = torch_dev
+    import ctypes
+    from paper_1510_04331_amd import _abi, ops
+    lib = _abi.load()
+    ctx = ops.context(0)
+    x = torch.zeros((2, 8, 8), device=dev)
+    d = torch.zeros(2, dtype=torch.float64, device=dev)
+    g = _abi.Geom(2, 7, 0, 0)
+    p = ctypes.c_void_p
+    assert lib.graphic_shift(ctx, ctypes.byref(g), p(x.data_ptr()), p(x.data_ptr()), p(d.data_ptr()),
+                             p(d.data_ptr()), None, None, 0, None) == _abi.ERR_ARG
+    g = _abi.Geom(2, 8, 0, 0)
+    # rotation needs a workspace
+    assert lib.graphic_rotate(ctx, ctypes.byref(g), p(x.data_ptr()), p(x.data_ptr()), p(d.data_ptr()),
+                              None, None, 0, None) == _abi.ERR_WORKSPACE
+    # partial overlap of input and output
+    big = torch.zeros((3, 8, 8), device=dev)
+    assert lib.graphic_shift(ctx, ctypes.byref(g), p(big.data_ptr()), p(big.data_ptr() + 4 * 64),
+                             p(d.data_ptr()), p(d.data_ptr()), None, None, 0, None) == _abi.ERR_ARG
+    torch.cuda.synchronize()
