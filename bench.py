@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the Fourier ADI hot path on one MI355X.
+
+One step = one classical ADI reduction (recentring shift of every frame,
+median PSF, subtraction, three-shear derotation, median combine) of a
+SPHERE-like cube of 4096 frames of 1024 x 1024 float32 (zero-padded to
+2048 x 2048), with the cube already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "frames shifted+rotated/s at 1024² FP32 (% HBM roofline); cube p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per frame of each kernel family (float32, N x N frames,
+# working size P): one read of every stored input value and one write of every
+# stored output value; zero padding is never read, cropped values never written.
+def alg_bytes_per_frame(fam, N, P, T):
+    n2, nP = N * N * 4, N * P * 4
+    return {
+        "shift_y": 2 * n2,
+        "shift_x": 2 * n2,
+        "shear_x1": n2 + nP,
+        "shear_y": 2 * nP,
+        "shear_x2": nP + n2,
+        "median": n2 + n2 / T,
+    }.get(fam)
+
+
+FAMILIES = ("shift_y", "shift_x", "shear_x1", "shear_y", "shear_x2", "median", "aux")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle, frames spread over a process pool (the
+# paper's temporal scheme).  Runs before the GPU is touched.
+# ---------------------------------------------------------------------------
+def _oracle_frame(args):
+    import numpy as np
+    import oracle as O
+    f, dx, dy, ang = args
+    s = O.shift(f, dx, dy)
+    r = O.rotate(s, -ang)
+    return float(np.sum(r))
+
+
+def cpu_baseline(frames_per_core=2):
+    import multiprocessing as mp
+    import synth
+    cores = min(os.cpu_count() or 1, 16)
+    p = synth.make_params(3)
+    idx = list(range(frames_per_core * cores))
+    frames = synth.render_host(p, frames=idx)
+    work = [(frames[i].astype("float64"), p.dx[i], p.dy[i], p.parang[i]) for i in range(len(idx))]
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_frame, work, chunksize=1)
+    dt = time.perf_counter() - t0
+    return {"value": len(idx) / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": "%d frames of the 4096 x 1024^2 cube (padded to 2048^2), float64 oracle shift + "
+                      "three-shear rotation per frame, one process per core (median steps excluded; "
+                      "they are O(T N^2) and under 1%% of the oracle's time); wall %.1f s"
+                      % (len(idx), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=4096)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                       "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (multi-GPU sharding is described in "
+              "DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+        print("cpu baseline: %.3f frames/s on %d cores" % (cpu["value"], cpu["cores"]), file=sys.stderr,
+              flush=True)
+
+    import numpy as np
+    import torch
+    import paper_1510_04331_amd as G
+    import synth
+
+    dev = torch.device("cuda:0")
+    p = synth.make_params(3, T=args.frames, N=args.size)
+    T, N, P = p.T, p.N, p.P
+    print("generating cube T=%d N=%d on the device" % (T, N), file=sys.stderr, flush=True)
+    cube = synth.render_device(p, dev)
+    dx = torch.tensor(p.dx, dtype=torch.float64, device=dev)
+    dy = torch.tensor(p.dy, dtype=torch.float64, device=dev)
+    pa = torch.tensor(p.parang, dtype=torch.float64, device=dev)
+    nws = G.workspace_size(2, T, N)
+    ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        G.adi_reduce(cube, dx, dy, pa, workspace=ws)
+    torch.cuda.synchronize()
+    print("warmup done", file=sys.stderr, flush=True)
+
+    G.timing_enable(True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        final = G.adi_reduce(cube, dx, dy, pa, workspace=ws)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t_all
+    fams = {}
+    for fam in FAMILIES:
+        ms, n = G.timing_read(fam)
+        if n:
+            fams[fam] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+                         "avg_launch_ms": ms / n}
+    G.timing_enable(False)
+    assert torch.isfinite(final).all()
+
+    ms_per_step = total_s * 1e3 / args.steps
+    value = T / (ms_per_step / 1e3)
+    # shift + rotate alone (the five line passes), from the per-kernel events
+    sr_ms = sum(fams[f]["ms_per_step"] for f in ("shift_y", "shift_x", "shear_x1", "shear_y", "shear_x2")
+                if f in fams)
+    for fam, d in fams.items():
+        b = alg_bytes_per_frame(fam, N, P, T)
+        if b is None:
+            continue
+        frames_per_launch = T / d["launches_per_step"]
+        d["alg_bytes_per_launch"] = b * frames_per_launch
+        d["achieved_GBps"] = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
+    dom = max((f for f in fams if "achieved_GBps" in fams[f]), key=lambda f: fams[f]["ms_per_step"])
+    traffic = None
+    try:
+        with open(args.traffic) as fh:
+            tr = json.load(fh)
+        ent = tr.get(dom)
+        if ent and ent.get("N") == N and ent.get("frames_per_launch") == T / fams[dom]["launches_per_step"]:
+            traffic = ent["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    sl = sorted(step_ms)
+
+    def pct(q):
+        return sl[min(len(sl) - 1, int(math.ceil(q * len(sl))) - 1)]
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "SPHERE-like ADI cube: %d frames %dx%d float32, zero-padded to %dx%d; full "
+                               "reduction (shift, median PSF, subtract, derotate, median combine)"
+                               % (T, N, N, P, P),
+                   "frames": T, "size": N, "pad": P, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(fams[dom]["achieved_GBps"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(fams[dom]["achieved_GBps"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(pct(0.5), 3), "p99": round(pct(0.99), 3)},
+        "shift_rotate_frames_per_s": round(T / (sr_ms / 1e3), 1) if sr_ms else None,
+        "shift_rotate_hbm_frac": round(56.0 * N * N * (T / (sr_ms / 1e3)) / (HBM_PEAK_GBS * 1e9), 4)
+        if sr_ms else None,
+        "kernels": {f: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+                    for f, d in fams.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,8 +173,10 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
 /* Per-kernel timing with HIP events on the caller's stream (for benchmarks).
  * When enabled, every library kernel launch is bracketed by events; the
  * accumulated milliseconds and launch counts per kernel family are read with
- * graphic_timing_read after the stream has been synchronised.  Names:
- * "col_pass", "row_pass", "median", "aux". */
+ * graphic_timing_read after the stream has been synchronised.  Families:
+ * "shift_y", "shift_x" (the two shift passes), "shear_x1", "shear_y",
+ * "shear_x2" (the three rotation passes), "median" and "aux" (per-frame
+ * parameters and flux sums).  Enabling (or disabling) clears the counters. */
 graphic_status graphic_timing_enable(graphic_ctx ctx, int enable);
 graphic_status graphic_timing_read(graphic_ctx ctx, const char* family,
                                    double* total_ms, int64_t* launches);

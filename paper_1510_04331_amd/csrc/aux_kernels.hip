@@ -45,7 +45,25 @@ __global__ void __launch_bounds__(256) frame_sums_kernel(const float* __restrict
   if (threadIdx.x == 0) flux[2 * f + slot] = part[0];
 }
 
+// Compacted list of the half-turned frames of one chunk (any order; each
+// listed frame is processed independently).
+__global__ void __launch_bounds__(256) flip_list_kernel(const int* __restrict__ flip, long long f0, long long n,
+                                                        int* __restrict__ list, int* __restrict__ count) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (long long i = threadIdx.x; i < n; i += 256)
+    if (flip[f0 + i] != 0) list[atomicAdd(&cnt, 1)] = (int)i;
+  __syncthreads();
+  if (threadIdx.x == 0) *count = cnt;
+}
+
 }  // namespace
+
+hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* list, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(flip_list_kernel, dim3(1), dim3(256), 0, s, flip, f0, n, list, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_rotation_params(const double* theta_deg, double sign, long long T, int* flip,
                                   double* neg_tan_half, double* sin_theta, hipStream_t s) {

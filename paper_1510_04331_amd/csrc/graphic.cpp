@@ -155,7 +155,9 @@ struct RotLayout {
 
 RotLayout rot_layout(long long T, int N, int P, size_t chunk_bytes, size_t avail /*0 = choose*/) {
   RotLayout L;
-  L.params = align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double));
+  // flip flags, -tan(theta/2), sin(theta), half-turned frame list, its count
+  L.params = align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double)) +
+             align_up((size_t)T * sizeof(int)) + kAlign;
   const size_t per_frame = (size_t)N * P * sizeof(float);
   size_t cf = avail ? (avail > L.params ? (avail - L.params) / per_frame : 0)
                     : std::max<size_t>(1, chunk_bytes / per_frame);
@@ -201,8 +203,8 @@ struct Timer {
 
 graphic_status hip_ok(hipError_t e) { return e == hipSuccess ? GRAPHIC_OK : GRAPHIC_ERR_HIP; }
 
-graphic_status run_pass(graphic_ctx ctx, const LinePass& p, int kind, hipStream_t st) {
-  Timer t(ctx, st, kind == kRowPass ? "row_pass" : "col_pass");
+graphic_status run_pass(graphic_ctx ctx, const LinePass& p, int kind, const char* family, hipStream_t st) {
+  Timer t(ctx, st, family);
   hipError_t e = launch_line_pass(p, kind, 0, st);
   t.done();
   return hip_ok(e);
@@ -237,14 +239,14 @@ graphic_status do_shift(graphic_ctx ctx, long long T, int N, int P, const float*
   c.n_jobs = N / 2;
   c.n_frames = T;
   c.sh0 = dy;
-  graphic_status s = run_pass(ctx, c, kColPass, st);
+  graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
   if (s != GRAPHIC_OK) return s;
   LinePass r = c;
   r.src = out;
   r.src_ls = r.dst_ls = N;
   r.src_ps = r.dst_ps = 1;
   r.sh0 = dx;
-  return run_pass(ctx, r, kRowPass, st);
+  return run_pass(ctx, r, kRowPass, "shift_x", st);
 }
 
 // Rotation of frames [0, T) of `src` into `dst` (may alias src), optionally
@@ -258,6 +260,8 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
   int* flip = reinterpret_cast<int*>(w);
   double* ntan = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)));
   double* sn = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)) + align_up((size_t)T * sizeof(double)));
+  int* flip_list = reinterpret_cast<int*>(w + align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double)));
+  int* flip_count = reinterpret_cast<int*>(reinterpret_cast<char*>(flip_list) + align_up((size_t)T * sizeof(int)));
   float* scratch = reinterpret_cast<float*>(w + L.params);
   {
     Timer t(ctx, st, "aux");
@@ -268,6 +272,12 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
   const int o = (P - N) / 2;
   for (long long f0 = 0; f0 < T; f0 += (long long)L.chunk_frames) {
     const long long nf = std::min<long long>((long long)L.chunk_frames, T - f0);
+    {
+      Timer t(ctx, st, "aux");
+      hipError_t e = launch_flip_list(flip, f0, nf, flip_list, flip_count, st);
+      t.done();
+      if (e != hipSuccess) return GRAPHIC_ERR_HIP;
+    }
     // x-shear 1: window rows -> all P columns of the scratch frame
     LinePass a = base_pass(ctx, P);
     a.src = src + f0 * (long long)N * N;
@@ -277,8 +287,7 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     a.dst_fs = (long long)N * P;
     a.src_ls = N;
     a.src_ps = 1;
-    a.sub_ls = N;
-    a.sub_ps = 1;
+    a.sub_bytes = sub ? (long long)N * N * 4 : 0;   // same (row, column) strides as the source
     a.dst_ls = P;
     a.dst_ps = 1;
     a.line_lo = o;
@@ -293,10 +302,12 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     a.n_frames = nf;
     a.sh1 = ntan + f0;
     a.flip = flip + f0;
+    a.flip_list = flip_list;
+    a.flip_count = flip_count;
     a.flip_src_reverse = 1;
     a.flip_lines = 1;
     a.flip_in_off = 1;
-    graphic_status s = run_pass(ctx, a, kRowPass, st);
+    graphic_status s = run_pass(ctx, a, kRowPass, "shear_x1", st);
     if (s != GRAPHIC_OK) return s;
     // y-shear: every scratch column, window rows in and out (in place)
     LinePass b = base_pass(ctx, P);
@@ -317,8 +328,10 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     b.n_frames = nf;
     b.sh1 = sn + f0;
     b.flip = flip + f0;
+    b.flip_list = flip_list;
+    b.flip_count = flip_count;
     b.flip_in_off = 1;
-    s = run_pass(ctx, b, kColPass, st);
+    s = run_pass(ctx, b, kColPass, "shear_y", st);
     if (s != GRAPHIC_OK) return s;
     // x-shear 2: window rows, all P columns in, window columns out
     LinePass c = base_pass(ctx, P);
@@ -341,7 +354,7 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     c.n_jobs = N / 2 + 1;
     c.n_frames = nf;
     c.sh1 = ntan + f0;
-    s = run_pass(ctx, c, kRowPass, st);
+    s = run_pass(ctx, c, kRowPass, "shear_x2", st);
     if (s != GRAPHIC_OK) return s;
   }
   return GRAPHIC_OK;

@@ -28,9 +28,11 @@ struct LinePass {
   // memory: element (frame f, line li, position pi) at base + f*fs + li*ls + pi*ps
   const float* src;
   float* dst;
-  const float* sub;       // nullable N x N frame subtracted from every source value
+  const float* sub;       // nullable N x N frame subtracted from every source value;
+                          // indexed with the source's own (line, position) strides
+  long long sub_bytes;
   long long src_fs, dst_fs;
-  int src_ls, src_ps, dst_ls, dst_ps, sub_ls, sub_ps;
+  int src_ls, src_ps, dst_ls, dst_ps;
 
   int P;                  // working size
   int line_lo;            // first line (padded coordinate) of the line set
@@ -42,6 +44,7 @@ struct LinePass {
   int mirror;             // 0: pair lines (l, l+1) with one shift; 1: pair (c-d, c+d)
   int n_jobs;             // jobs (line pairs) per frame
   long long n_frames;
+  int blocks_per_frame;   // set by the launcher: blocks never straddle frames
 
   // shift of line l in frame f: sh0[f] + sh1[f] * (l - P/2)   (either may be null)
   const double* sh0;
@@ -49,6 +52,8 @@ struct LinePass {
 
   // per-frame half-turn flag (nullable) and where it acts
   const int* flip;
+  const int* flip_list;   // indices of the half-turned frames (relative to this pass's frames)
+  const int* flip_count;  // their number (device memory)
   int flip_src_reverse;   // source array read reversed along and across lines
   int flip_lines;         // line set and destination lines start one later
   int flip_in_off;        // source support starts one later
@@ -58,12 +63,20 @@ struct LinePass {
 
 enum PassKind { kRowPass = 0, kColPass = 1 };
 
+// Index patterns of a pass (input support -> output window), see line_pass.hip.
+enum IoKind { kIoGeneric = 0, kIoWinWin = 1, kIoWinFull = 2, kIoFullWin = 3 };
+
 hipError_t launch_line_pass(const LinePass& p, int kind, int jobs_per_block, hipStream_t s);
 
 // Per-frame rotation parameters from angles: flip (|theta| > 90), -tan(theta'/2), sin(theta').
 hipError_t launch_rotation_params(const double* theta_deg, double sign, long long T,
                                   int* flip, double* neg_tan_half, double* sin_theta,
                                   hipStream_t s);
+
+// Compacted list of the frames f0 <= f < f0 + n with flip[f] != 0, as indices
+// relative to f0, and their count.
+hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* list, int* count,
+                            hipStream_t s);
 
 // Exact per-pixel median of a [T][npix] stack -> [npix].
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, hipStream_t s);

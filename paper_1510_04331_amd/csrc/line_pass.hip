@@ -21,13 +21,22 @@
 // stage is done as an unfold that writes only the requested output window.
 //
 // The even-bin half of a job runs on Ma lanes and the odd-bin half on the next
-// Ma lanes; every lane holds Mb complex values.
+// Ma lanes; every lane holds Mb complex values.  LDS exchanges move the real
+// parts and then the imaginary parts through one float buffer, which halves
+// the LDS footprint per wave.
+//
+// Memory access: blocks never straddle frames, so every base address is
+// wave-uniform and all loads and stores are bounds-checked buffer
+// instructions: an offset outside the frame reads 0 (the zero padding) and a
+// store outside it is dropped, which keeps the kernel free of branches.
 //
 // Phasor: bin k of the length-P transform (signed index kt) gets
 // exp(-2 pi i kt s / P); the Nyquist bin gets cos(pi s).  The phase kt*s/P is
 // formed and reduced modulo one in float64 as kt = (2 k2 + h) + 2 Mb k1' with
 // a per-lane factor for (2 k2 + h) and a per-job table over k1', each entry
 // evaluated from its own float64-reduced phase.
+
+#include <algorithm>
 
 #include "dft_codelets.h"
 #include "internal.h"
@@ -40,36 +49,75 @@ struct Shape {
   static constexpr int Ma = 1 << (lg / 2);
   static constexpr int Mb = M / Ma;
   static constexpr int JOB = 2 * Ma;
-  static constexpr int ROWP = Ma + 1;                  // padded LDS row (complex)
-  static constexpr int HALF = Mb * ROWP;               // complex per half-job
-  static constexpr int PER_JOB = 2 * HALF + Ma;        // + phasor table
+  static constexpr int ROWP = Ma + 1;                  // padded LDS row (floats)
+  static constexpr int HALF = Mb * ROWP;               // floats per half-job
+  static constexpr int PER_JOB_F = 2 * HALF + 2 * Ma;  // + phasor table (complex)
   static_assert(Mb == Ma || Mb == 2 * Ma, "square or 1:2 four-step split");
 };
 
-// float64 reduction of kk * q modulo one, then float32 sin/cos of the residue.
+// ---------------------------------------------------------------------------
+// exp(-2 pi i * kk * q) * scale with the phase reduced in float64:
+// ph = kk*q mod 1 in [-1/2, 1/2], then the nearest quarter turn is taken out
+// (so the float32 angle is at most pi/4) and sin/cos come from their Taylor
+// series (remainders below 2e-9 on [-pi/4, pi/4]).
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
   double ph = kk * q;
-  ph = ph - rint(ph);                       // |ph| <= 1/2 cycle
-  float a = (float)(ph * -6.283185307179586476925);
-  float sn, cs;
-  sincosf(a, &sn, &cs);
-  return {cs * scale, sn * scale};
+  ph -= rint(ph);
+  const double qt = rint(4.0 * ph);                   // quarter turns, -2..2
+  const float a = (float)((ph - 0.25 * qt) * -6.283185307179586476925);
+  const float a2 = a * a;
+  float sn = fmaf(a2, 2.7557319e-6f, -1.9841270e-4f);
+  sn = fmaf(a2, sn, 8.3333333e-3f);
+  sn = fmaf(a2, sn, -1.6666667e-1f);
+  sn = a * fmaf(a2, sn, 1.0f);
+  float cs = fmaf(a2, -2.7557319e-7f, 2.4801587e-5f);
+  cs = fmaf(a2, cs, -1.3888889e-3f);
+  cs = fmaf(a2, cs, 4.1666667e-2f);
+  cs = fmaf(a2, cs, -0.5f);
+  cs = fmaf(a2, cs, 1.0f);
+  // exp(-i 2 pi (r + qt/4)) = exp(-i 2 pi r) * (-i)^qt
+  const int qi = ((int)qt) & 3;
+  float re = cs, im = sn;
+  if (qi == 1) { re = sn; im = -cs; }
+  else if (qi == 2) { re = -cs; im = -sn; }
+  else if (qi == 3) { re = -sn; im = cs; }
+  return {re * scale, im * scale};
 }
 
-// Occupancy target (waves per SIMD) that bounds the register budget; the LDS
-// footprint (about 17 KB per wave for M >= 512) allows no more than this.
+// Occupancy target (waves per SIMD) that bounds the register budget.
 template <int M>
 constexpr int waves_per_eu() {
-  return M <= 1024 ? 4 : 2;
+  return M <= 256 ? 4 : (M == 1024 ? 3 : 2);
 }
 
-template <int M, int KIND, int G>
-__global__ void __launch_bounds__(G * Shape<M>::JOB, waves_per_eu<M>())
-line_pass_kernel(const LinePass p) {
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, int soff = 0) {
+  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
+}
+__device__ __forceinline__ cf buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off, int soff) {
+  const v2i t = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0);
+  return {__int_as_float(t.x), __int_as_float(t.y)};
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float v, int soff = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, soff, 0);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  // third dword of the gfx9 buffer descriptor: 32-bit raw data, bounds-checked
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr unsigned kOOB = 0x80000000u;   // beyond every frame: reads 0, writes dropped
+
+// One block of jobs: frame f, jobs [jb*G, jb*G + G) of that frame.
+template <int M, int KIND, int G, int IO>
+__device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
-  extern __shared__ float2 lds_raw[];
-  cf* lds = reinterpret_cast<cf*>(lds_raw);
+  extern __shared__ float lds_raw[];
+  float* lds = lds_raw;
+  cf* ptab = reinterpret_cast<cf*>(lds_raw + G * 2 * S::HALF);
 
   const int tid = threadIdx.x;
   int jl, r;
@@ -83,40 +131,28 @@ line_pass_kernel(const LinePass p) {
   const int h = r / Ma;        // 0: even bins, 1: odd bins
   const int n1 = r % Ma;
 
-  // LDS addressing: (job, half, row k2, column n1); the column kernel keeps the
-  // job index fastest so that lanes of one wave (consecutive jobs) hit
-  // consecutive words.
+  // LDS float addressing: (job, half, row k2, column c); the column kernel
+  // keeps the job index fastest so that lanes of one wave (consecutive jobs)
+  // hit consecutive words.
   auto lidx = [&](int hh, int k2, int c) -> int {
     if constexpr (KIND == kRowPass)
       return (jl * 2 + hh) * S::HALF + k2 * S::ROWP + c;
     else
       return ((hh * Mb + k2) * S::ROWP + c) * G + jl;
   };
-  auto tidx = [&](int k1) -> int {   // phasor table of the job
+  auto tidx = [&](int k1) -> int {
     if constexpr (KIND == kRowPass)
-      return G * 2 * S::HALF + jl * Ma + k1;
+      return jl * Ma + k1;
     else
-      return G * 2 * S::HALF + k1 * G + jl;
+      return k1 * G + jl;
   };
 
-  // XCD-aware block order: the hardware deals consecutive block ids to the
-  // eight XCDs in turn; remap so that each XCD walks a contiguous range of jobs
-  // (neighbouring lines share cache lines in its L2).
-  long long nb = gridDim.x;
-  long long b = blockIdx.x;
-  long long per = (nb + 7) / 8;
-  long long lb = (b % 8) * per + b / 8;
-  if (nb % 8 != 0) lb = b;   // keep it simple when the grid does not split evenly
-
-  const long long total = p.n_frames * (long long)p.n_jobs;
-  const long long gj = lb * G + jl;
-  const bool job_ok = gj < total;
-  const long long f = job_ok ? gj / p.n_jobs : 0;
-  const int j = job_ok ? (int)(gj % p.n_jobs) : 0;
+  const int j = (int)jb * G + jl;
+  const bool job_ok = j < p.n_jobs;
 
   const int P = p.P;
   const int c = P / 2;
-  const int flipf = (p.flip != nullptr && job_ok) ? (p.flip[f] != 0) : 0;
+  const int flipf = p.flip != nullptr ? (p.flip[f] != 0) : 0;
   const int line_lo = p.line_lo + (p.flip_lines ? flipf : 0);
   // Line coordinates are periodic (mod P): with P = N a half-turned frame's
   // support wraps, and padded line P is line 0 (shift -c * coef).
@@ -135,138 +171,249 @@ line_pass_kernel(const LinePass p) {
   const bool a_ok = job_ok && ra < p.n_lines;
   const bool b_ok = job_ok && b_exists && rb < p.n_lines;
   double s = 0.0;
-  if (job_ok) {
-    if (p.sh0) s += p.sh0[f];
-    if (p.sh1) s += p.sh1[f] * (double)(la - c);
-  }
+  if (p.sh0) s += p.sh0[f];
+  if (p.sh1) s += p.sh1[f] * (double)(la - c);
   const double q = s / (double)P;
 
   const int in_off = p.in_off + (p.flip_in_off ? flipf : 0);
   const int L = p.in_len;
   const int R = 2 * in_off + L - 1;
   const bool rev = p.flip_src_reverse && flipf;
+  const bool rev_b = p.mirror ? !rev : rev;
   const int lia = rev ? (p.n_lines - 1 - ra) : ra;
   const int lib = rev ? (p.n_lines - 1 - rb) : rb;
-  const float* srcf = p.src + f * p.src_fs;
-  const float* rowa = srcf + (long long)lia * p.src_ls;
-  const float* rowb = srcf + (long long)lib * p.src_ls;
-  const float* suba = p.sub ? p.sub + (long long)lia * p.sub_ls : nullptr;
-  const float* subb = p.sub ? p.sub + (long long)lib * p.sub_ls : nullptr;
-  const bool rev_b = p.mirror ? !rev : rev;
 
-  // ---- per-job phasor table over k1 (written now, read after the transpose) ----
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(p.src + (size_t)f * p.src_fs, (unsigned)p.src_fs * 4u);
+  const __amdgpu_buffer_rsrc_t sub = make_rsrc(p.sub, p.sub ? (unsigned)p.sub_bytes : 0u);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc(p.dst + (size_t)f * p.dst_fs, (unsigned)p.dst_fs * 4u);
+  const __amdgpu_buffer_rsrc_t tfold = make_rsrc(p.tw.fold, 2u * M * 8u);
+  const __amdgpu_buffer_rsrc_t tfwd = make_rsrc(p.tw.fwd, (unsigned)M * 8u);
+  const __amdgpu_buffer_rsrc_t tinv = make_rsrc(p.tw.inv, (unsigned)M * 8u);
+  const unsigned ls4 = (unsigned)p.src_ls * 4u;
+  const int ps4 = p.src_ps * 4;
+  const unsigned base_a = a_ok ? (unsigned)lia * ls4 : kOOB;
+  const unsigned base_b = b_ok ? (unsigned)lib * ls4 : kOOB;
+  const bool has_sub = p.sub != nullptr;
+  // the canonical geometries (P = 2N, frame not half-turned) use static
+  // index patterns; everything else takes the general path
+  constexpr bool fast = IO != kIoGeneric;
+
+  // ---- per-job phasor table over k1 (read after the first exchange) ----
   if (h == 0) {
     const int k1s = n1 < Ma / 2 ? n1 : n1 - Ma;
-    lds[tidx(n1)] = phase_exp((double)(2 * Mb) * (double)k1s, q, 1.0f / (float)P);
+    ptab[tidx(n1)] = phase_exp((double)(2 * Mb) * (double)k1s, q, 1.0f / (float)P);
   }
 
   // ---- load, pack and fold into this half's branch ----
+  const float sg = h ? -1.0f : 1.0f;
+  const unsigned tw_lane = (unsigned)(h * M + n1) * 8u;
   cf v[Mb];
+  if constexpr (fast && (IO == kIoWinWin || IO == kIoWinFull)) {
+    // support [M/2, 3M/2): element m = n1 + Ma n2 has exactly one valid
+    // candidate, position u = n1 + Ma ((n2 + Mb/2) mod Mb) of the source line
+    const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
+    const unsigned lb_lane = base_b + (unsigned)((p.mirror ? (Ma - 1 - n1) : n1) * ps4);
 #pragma unroll
-  for (int n2 = 0; n2 < Mb; ++n2) {
-    const int m = n1 + Ma * n2;
-    cf z[2];
-#pragma unroll
-    for (int cnd = 0; cnd < 2; ++cnd) {
-      const int n = m + cnd * M;
-      const int u = (n - in_off + P) & (P - 1);
-      float av = 0.f, bv = 0.f;
-      if (u < L) {
-        const int pa = rev ? (L - 1 - u) : u;
-        const int pb = rev_b ? (L - 1 - u) : u;
-        if (a_ok) {
-          av = rowa[(long long)pa * p.src_ps];
-          if (suba) av -= suba[(long long)pa * p.sub_ps];
-        }
-        if (b_ok) {
-          bv = rowb[(long long)pb * p.src_ps];
-          if (subb) bv -= subb[(long long)pb * p.sub_ps];
-        }
+    for (int n2 = 0; n2 < Mb; ++n2) {
+      const int k = (n2 + Mb / 2) % Mb;
+      const int sa = Ma * k * ps4;
+      const int sb = (p.mirror ? Ma * (Mb - 1 - k) : Ma * k) * ps4;
+      float av = buf_ld(src, la_lane, sa), bv = buf_ld(src, lb_lane, sb);
+      if (has_sub) {
+        av -= buf_ld(sub, la_lane, sa);
+        bv -= buf_ld(sub, lb_lane, sb);
       }
-      z[cnd] = {av, bv};
+      const float sc = n2 < Mb / 2 ? sg : 1.0f;    // the valid candidate is n = m + M below Mb/2
+      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
+      v[n2] = cmul({sc * av, sc * bv}, w);
     }
-    const float2 w = p.tw.fold[h * M + m];
-    const cf x = h ? csub(z[0], z[1]) : cadd(z[0], z[1]);
-    v[n2] = cmul(x, {w.x, w.y});
+  } else if constexpr (fast && IO == kIoFullWin) {
+    // support [0, P): both candidates n = m and n = m + M are valid
+    const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
+    const unsigned lb_lane = base_b + (unsigned)((p.mirror ? (Ma - 1 - n1) : n1) * ps4);
+#pragma unroll
+    for (int n2 = 0; n2 < Mb; ++n2) {
+      const int sa0 = Ma * n2 * ps4, sa1 = (Ma * n2 + M) * ps4;
+      const int sb0 = (p.mirror ? Ma * (2 * Mb - 1 - n2) : Ma * n2) * ps4;
+      const int sb1 = (p.mirror ? Ma * (Mb - 1 - n2) : Ma * n2 + M) * ps4;
+      const float a0 = buf_ld(src, la_lane, sa0), a1 = buf_ld(src, la_lane, sa1);
+      const float b0 = buf_ld(src, lb_lane, sb0), b1 = buf_ld(src, lb_lane, sb1);
+      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
+      v[n2] = cmul({fmaf(sg, a1, a0), fmaf(sg, b1, b0)}, w);
+    }
+  } else {
+#pragma unroll
+    for (int n2 = 0; n2 < Mb; ++n2) {
+      const int m = n1 + Ma * n2;
+      cf z[2];
+#pragma unroll
+      for (int cnd = 0; cnd < 2; ++cnd) {
+        const int n = m + cnd * M;
+        const int u = (n - in_off + P) & (P - 1);
+        const bool in = u < L;
+        const unsigned pa = (unsigned)(rev ? (L - 1 - u) : u);
+        const unsigned pb = (unsigned)(rev_b ? (L - 1 - u) : u);
+        const unsigned oa = in ? base_a + pa * (unsigned)ps4 : kOOB;
+        const unsigned ob = in ? base_b + pb * (unsigned)ps4 : kOOB;
+        float av = buf_ld(src, oa), bv = buf_ld(src, ob);
+        if (has_sub) {
+          av -= buf_ld(sub, oa);
+          bv -= buf_ld(sub, ob);
+        }
+        z[cnd] = {av, bv};
+      }
+      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
+      v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
+    }
   }
 
-  // ---- step A: length-Mb transforms over n2, twiddle, transpose ----
+  // ---- step A: length-Mb transforms over n2, twiddle ----
   Dft<Mb, -1>::run(v);
 #pragma unroll
-  for (int k2 = 0; k2 < Mb; ++k2) {
-    const float2 w = p.tw.fwd[k2 * Ma + n1];
-    lds[lidx(h, k2, n1)] = cmul(v[k2], {w.x, w.y});
+  for (int k2 = 0; k2 < Mb; ++k2) v[k2] = cmul(v[k2], buf_ld2(tfwd, (unsigned)n1 * 8u, k2 * Ma * 8));
+
+  // ---- exchange 1 (real parts, then imaginary parts) ----
+  constexpr int NQ = Mb / Ma;
+  cf wv[NQ][Ma];
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (part) __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < Mb; ++k2) lds[lidx(h, k2, n1)] = part ? v[k2].y : v[k2].x;
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+      for (int c1 = 0; c1 < Ma; ++c1) {
+        const float t = lds[lidx(h, n1 + Ma * qq, c1)];
+        if (part) wv[qq][c1].y = t;
+        else wv[qq][c1].x = t;
+      }
   }
-  __syncthreads();
 
   // ---- step C: length-Ma transforms over n1, phasor, inverse, twiddle ----
-  constexpr int NQ = Mb / Ma;
 #pragma unroll
   for (int qq = 0; qq < NQ; ++qq) {
     const int k2 = n1 + Ma * qq;
-    cf w[Ma];
-#pragma unroll
-    for (int c1 = 0; c1 < Ma; ++c1) w[c1] = lds[lidx(h, k2, c1)];
+    cf* w = wv[qq];
     Dft<Ma, -1>::run(w);
     const cf tlo = phase_exp((double)(2 * k2 + h), q, 1.0f);
     const bool nyq_lane = (h == 0) && (k2 == 0);
 #pragma unroll
     for (int k1 = 0; k1 < Ma; ++k1) {
-      cf ph = cmul(tlo, lds[tidx(k1)]);
+      cf ph = cmul(tlo, ptab[tidx(k1)]);
       if (k1 == Ma / 2 && nyq_lane) ph.y = 0.f;   // real, symmetric Nyquist term
       w[k1] = cmul(w[k1], ph);
     }
     Dft<Ma, +1>::run(w);
 #pragma unroll
-    for (int c1 = 0; c1 < Ma; ++c1) v[qq * Ma + c1] = w[c1];
+    for (int c1 = 0; c1 < Ma; ++c1) w[c1] = cmul(w[c1], buf_ld2(tinv, (unsigned)n1 * 8u, (c1 * Mb + Ma * qq) * 8));
   }
-  __syncthreads();
+
+  // ---- exchange 2 ----
 #pragma unroll
-  for (int qq = 0; qq < NQ; ++qq) {
-    const int k2 = n1 + Ma * qq;
+  for (int part = 0; part < 2; ++part) {
+    __syncthreads();
 #pragma unroll
-    for (int c1 = 0; c1 < Ma; ++c1) {
-      const float2 t = p.tw.inv[c1 * Mb + k2];
-      lds[lidx(h, k2, c1)] = cmul(v[qq * Ma + c1], {t.x, t.y});
+    for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+      for (int c1 = 0; c1 < Ma; ++c1) lds[lidx(h, n1 + Ma * qq, c1)] = part ? wv[qq][c1].y : wv[qq][c1].x;
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < Mb; ++k2) {
+      const float t = lds[lidx(h, k2, n1)];
+      if (part) v[k2].y = t;
+      else v[k2].x = t;
     }
   }
-  __syncthreads();
 
   // ---- step A': length-Mb inverse transforms over k2 ----
-#pragma unroll
-  for (int k2 = 0; k2 < Mb; ++k2) v[k2] = lds[lidx(h, k2, n1)];
   Dft<Mb, +1>::run(v);
-  __syncthreads();
 
-  // ---- unfold: combine the even- and odd-bin halves ----
+  // ---- unfold: y[m] = e + W o and y[m + M] = e - W o with W = exp(+2 pi i m/P).
+  // The odd half applies W to its own values first; then each half sends its
+  // value X (e, or W o) to the other and forms y = sg * X_own + X_other, whose
+  // real part is line a and imaginary part line b' at position n = m + h M. ----
 #pragma unroll
-  for (int n2 = 0; n2 < Mb; ++n2) lds[lidx(h, n2, n1)] = v[n2];
-  __syncthreads();
+  for (int n2 = 0; n2 < Mb; ++n2) v[n2] = cmulc(v[n2], buf_ld2(tfold, tw_lane, Ma * n2 * 8));
 
   const int dst_lo = p.dst_line_lo + (p.flip_lines ? flipf : 0);
-  const int out_line_a = (la - dst_lo + P) & (P - 1);
-  const int out_line_b = (lb2 - dst_lo + P) & (P - 1);
-  float* dstf = p.dst + f * p.dst_fs;
-  float* oa = dstf + (long long)out_line_a * p.dst_ls;
-  float* ob = dstf + (long long)out_line_b * p.dst_ls;
+  const unsigned dls4 = (unsigned)p.dst_ls * 4u;
+  const int dps4 = p.dst_ps * 4;
+  const unsigned obase_a = a_ok ? (unsigned)((la - dst_lo + P) & (P - 1)) * dls4 : kOOB;
+  const unsigned obase_b = b_ok ? (unsigned)((lb2 - dst_lo + P) & (P - 1)) * dls4 : kOOB;
 #pragma unroll
-  for (int n2 = 0; n2 < Mb; ++n2) {
-    const int m = n1 + Ma * n2;
-    const cf oth = lds[lidx(1 - h, n2, n1)];
-    const cf own = v[n2];
-    const float2 t = p.tw.fold[M + m];
-    const cf e = h ? oth : own;
-    const cf o = h ? own : oth;
-    const cf wo = cmulc(o, {t.x, t.y});               // o * exp(+2 pi i m / P)
-    const cf y = h ? csub(e, wo) : cadd(e, wo);
-    const int n = m + h * M;
-    const int ua = n - p.out_off;
-    if (a_ok && ua >= 0 && ua < p.out_len) oa[(long long)ua * p.dst_ps] = y.x;
-    if (b_ok) {
-      const int nb_ = p.mirror ? ((R - n) % P + P) % P : n;
-      const int ub = nb_ - p.out_off;
-      if (ub >= 0 && ub < p.out_len) ob[(long long)ub * p.dst_ps] = y.y;
+  for (int part = 0; part < 2; ++part) {
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < Mb; ++n2) lds[lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
+    __syncthreads();
+    const unsigned obase = part ? obase_b : obase_a;
+    if constexpr (fast && (IO == kIoWinWin || IO == kIoFullWin)) {
+      // window [M/2, 3M/2): half h writes n2 >= Mb/2 (h = 0) or n2 < Mb/2 (h = 1),
+      // at window position n1 + Ma ((n2 + Mb/2) mod Mb) (reversed for line b')
+      const bool rv = part && p.mirror;
+      const unsigned lane = obase + (unsigned)((rv ? (Ma - 1 - n1) : n1) * dps4);
+#pragma unroll
+      for (int n2 = 0; n2 < Mb; ++n2) {
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        const int k = (n2 + Mb / 2) % Mb;
+        const bool mine = (n2 >= Mb / 2) == (h == 0);
+        buf_st(dst, mine ? lane : kOOB, y, (rv ? Ma * (Mb - 1 - k) : Ma * k) * dps4);
+      }
+    } else if constexpr (fast && IO == kIoWinFull) {
+      // all P positions: n = m + h M (reversed, P - 1 - n, for line b')
+      const bool rv = part && p.mirror;
+      const unsigned lane =
+          obase + (unsigned)((rv ? (Ma - 1 - n1) + (1 - h) * M : n1 + h * M) * dps4);
+#pragma unroll
+      for (int n2 = 0; n2 < Mb; ++n2) {
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        buf_st(dst, lane, y, (rv ? Ma * (Mb - 1 - n2) : Ma * n2) * dps4);
+      }
+    } else {
+#pragma unroll
+      for (int n2 = 0; n2 < Mb; ++n2) {
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        const int n = n1 + Ma * n2 + h * M;
+        const int pos = (part && p.mirror) ? ((R - n) % P + P) % P : n;
+        const int u = pos - p.out_off;
+        buf_st(dst, (u >= 0 && u < p.out_len) ? obase + (unsigned)(u * dps4) : kOOB, y);
+      }
     }
+  }
+}
+
+// Canonical-geometry and general kernels over a regular grid.  The hardware
+// deals consecutive block ids to the eight XCDs in turn; the remap gives each
+// XCD a contiguous range of blocks, so neighbouring lines share its L2.  When
+// the pass reads half-turned frames through a different support (first shear
+// and column shear of a rotation), those frames are skipped here and handled
+// by line_pass_flipped_kernel.
+template <int M, int KIND, int G, int IO>
+__global__ void __launch_bounds__(G * Shape<M>::JOB, waves_per_eu<M>())
+line_pass_kernel(const LinePass p) {
+  const unsigned nb = gridDim.x;
+  const unsigned b = blockIdx.x;
+  const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const unsigned f = lb / (unsigned)p.blocks_per_frame;
+  const unsigned jb = lb - f * (unsigned)p.blocks_per_frame;
+  if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
+    return;   // whole block leaves together, before any barrier
+  process_block<M, KIND, G, IO>(p, f, jb);
+}
+
+// General path for the half-turned frames listed in p.flip_list (count in
+// p.flip_count): a fixed grid walks the (frame, block) pairs.
+template <int M, int KIND, int G>
+__global__ void __launch_bounds__(G * Shape<M>::JOB, waves_per_eu<M>())
+line_pass_flipped_kernel(const LinePass p) {
+  const unsigned bpf = (unsigned)p.blocks_per_frame;
+  const unsigned work = (unsigned)(*p.flip_count) * bpf;
+  for (unsigned w = blockIdx.x; w < work; w += gridDim.x) {
+    const unsigned f = (unsigned)p.flip_list[w / bpf];
+    process_block<M, KIND, G, kIoGeneric>(p, f, w % bpf);
+    __syncthreads();
   }
 }
 
@@ -277,9 +424,9 @@ line_pass_kernel(const LinePass p) {
 template <int M>
 constexpr int col_jobs_per_block() {
   using S = Shape<M>;
-  constexpr int budget = 140 * 1024;
+  constexpr int budget = 80 * 1024;
   int g = 16;
-  while (g > 1 && (g * S::PER_JOB * 8 > budget || g * S::JOB > 1024)) g /= 2;
+  while (g > 1 && (g * S::PER_JOB_F * 4 > budget || g * S::JOB > 1024)) g /= 2;
   return g;
 }
 
@@ -288,28 +435,56 @@ constexpr int row_jobs_per_block() {
   return 64 / Shape<M>::JOB > 0 ? 64 / Shape<M>::JOB : 1;
 }
 
+template <int M, int KIND, int G, int IO>
+static hipError_t launch_g(LinePass p, hipStream_t st) {
+  using S = Shape<M>;
+  p.blocks_per_frame = (p.n_jobs + G - 1) / G;
+  const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const size_t lds = (size_t)G * S::PER_JOB_F * sizeof(float);
+  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || IO == kIoGeneric || p.flip == nullptr || !(p.flip_in_off || p.flip_src_reverse))
+    return e;
+  // half-turned frames: general path over the device-side list
+  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const long long fb = std::min<long long>(blocks, 2048);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
+  return hipGetLastError();
+}
+
+// Index pattern of a pass: the canonical window is [M/2, 3M/2) of the padded
+// line (P = 2N); "full" is the whole padded line.
+static int io_kind(const LinePass& p) {
+  const int M = p.P / 2;
+  const bool win_in = p.in_off == M / 2 && p.in_len == M;
+  const bool full_in = p.in_off == 0 && p.in_len == p.P;
+  const bool win_out = p.out_off == M / 2 && p.out_len == M;
+  const bool full_out = p.out_off == 0 && p.out_len == p.P;
+  if (M < 16) return kIoGeneric;
+  if (win_in && win_out) return kIoWinWin;
+  if (win_in && full_out) return kIoWinFull;
+  if (full_in && win_out && !p.flip) return kIoFullWin;
+  return kIoGeneric;
+}
+
+template <int M, int KIND, int G>
+static hipError_t launch_io(const LinePass& p, hipStream_t st) {
+  switch (io_kind(p)) {
+    case kIoWinWin: return launch_g<M, KIND, G, kIoWinWin>(p, st);
+    case kIoWinFull: return launch_g<M, KIND, G, kIoWinFull>(p, st);
+    case kIoFullWin: return launch_g<M, KIND, G, kIoFullWin>(p, st);
+    default: return launch_g<M, KIND, G, kIoGeneric>(p, st);
+  }
+}
+
 template <int M>
 static hipError_t launch_m(const LinePass& p, int kind, hipStream_t st) {
-  using S = Shape<M>;
-  const long long total = p.n_frames * (long long)p.n_jobs;
-  if (kind == kRowPass) {
-    constexpr int G = row_jobs_per_block<M>();
-    const long long blocks = (total + G - 1) / G;
-    const size_t lds = (size_t)G * S::PER_JOB * sizeof(cf);
-    hipFuncSetAttribute((const void*)line_pass_kernel<M, kRowPass, G>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((line_pass_kernel<M, kRowPass, G>), dim3((unsigned)blocks), dim3(G * S::JOB),
-                       lds, st, p);
-  } else {
-    constexpr int G = col_jobs_per_block<M>();
-    const long long blocks = (total + G - 1) / G;
-    const size_t lds = (size_t)G * S::PER_JOB * sizeof(cf);
-    hipFuncSetAttribute((const void*)line_pass_kernel<M, kColPass, G>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((line_pass_kernel<M, kColPass, G>), dim3((unsigned)blocks), dim3(G * S::JOB),
-                       lds, st, p);
-  }
-  return hipGetLastError();
+  if (kind == kRowPass) return launch_io<M, kRowPass, row_jobs_per_block<M>()>(p, st);
+  return launch_io<M, kColPass, col_jobs_per_block<M>()>(p, st);
 }
 
 hipError_t launch_line_pass(const LinePass& p, int kind, int /*jobs_per_block*/, hipStream_t s) {
