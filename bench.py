@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of the cube (known bytes) before the timed steps, "
+                         "to scale hardware byte counters")
     ap.add_argument("--traffic", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                        "profiles", "traffic.json"))
     args = ap.parse_args()
@@ -110,6 +113,13 @@ def main():
     ws = torch.empty(nws, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    if args.calibrate_copy:
+        scratch = torch.empty_like(cube)
+        scratch.copy_(cube)
+        torch.cuda.synchronize()
+        print("copy calibration: %d bytes read, %d bytes written" % (cube.numel() * 4, cube.numel() * 4),
+              file=sys.stderr, flush=True)
+        del scratch
     for _ in range(args.warmup):
         G.adi_reduce(cube, dx, dy, pa, workspace=ws)
     torch.cuda.synchronize()

@@ -34,9 +34,10 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, verbose, defines=()):
+    tag = "_".join(d.replace("=", "") for d in defines)
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + (("_" + tag) if tag else "") + ".o")
+    cmd = [_hipcc()] + COMMON + DEVICE + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,20 +46,22 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=4):
-    """Compile every source and link libgraphic.so next to this file."""
+def build(verbose=False, jobs=4, out=None, defines=()):
+    """Compile every source and link libgraphic.so next to this file (or to
+    ``out``), with optional extra ``-D`` definitions."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, defines), SOURCES))
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed\n%s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

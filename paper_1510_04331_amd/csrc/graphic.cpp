@@ -360,9 +360,10 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
   return GRAPHIC_OK;
 }
 
-graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, hipStream_t st) {
+graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, float* resid,
+                         hipStream_t st) {
   Timer t(ctx, st, "median");
-  hipError_t e = launch_median(stack, T, (long long)N * N, out, st);
+  hipError_t e = launch_median(stack, T, (long long)N * N, out, resid, st);
   t.done();
   return hip_ok(e);
 }
@@ -512,7 +513,7 @@ graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const f
       (out >= stack && out < stack + (size_t)T * N * N))
     return GRAPHIC_ERR_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
-  return do_median(ctx, T, N, stack, out, static_cast<hipStream_t>(stream));
+  return do_median(ctx, T, N, stack, out, nullptr, static_cast<hipStream_t>(stream));
 }
 
 graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, const float* cube, const double* dx,
@@ -548,10 +549,12 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, con
   void* rot_ws = w + stack_b + psf_b;
   const size_t rot_bytes = ws_bytes - stack_b - psf_b;
   if ((s = do_shift(ctx, T, N, P, cube, stack, dx, dy, st)) != GRAPHIC_OK) return s;
-  if ((s = do_median(ctx, T, N, stack, psf_buf, st)) != GRAPHIC_OK) return s;
-  if ((s = do_rotate(ctx, T, N, P, stack, psf_buf, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
+  // the PSF median also rewrites the stack as residuals S_i - PSF (Sect. 3.3),
+  // so the rotation reads them directly
+  if ((s = do_median(ctx, T, N, stack, psf_buf, stack, st)) != GRAPHIC_OK) return s;
+  if ((s = do_rotate(ctx, T, N, P, stack, nullptr, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
     return s;
-  return do_median(ctx, T, N, stack, final_img, st);
+  return do_median(ctx, T, N, stack, final_img, nullptr, st);
 }
 
 graphic_status graphic_timing_enable(graphic_ctx ctx, int enable) {

@@ -78,8 +78,10 @@ hipError_t launch_rotation_params(const double* theta_deg, double sign, long lon
 hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* list, int* count,
                             hipStream_t s);
 
-// Exact per-pixel median of a [T][npix] stack -> [npix].
-hipError_t launch_median(const float* stack, long long T, long long npix, float* out, hipStream_t s);
+// Exact per-pixel median of a [T][npix] stack -> [npix]; with resid non-null,
+// every value is also written back as value - median (resid may be stack).
+hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
+                         hipStream_t s);
 
 // Per-frame float64 sums of [T][N][N] frames into flux[2*t + slot].
 hipError_t launch_frame_sums(const float* frames, long long T, int N, double* flux, int slot,

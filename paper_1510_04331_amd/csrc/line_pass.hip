@@ -52,6 +52,7 @@ struct Shape {
   static constexpr int ROWP = Ma + 1;                  // padded LDS row (floats)
   static constexpr int HALF = Mb * ROWP;               // floats per half-job
   static constexpr int PER_JOB_F = 2 * HALF + 2 * Ma;  // + phasor table (complex)
+  static constexpr int PER_JOB_F_DB = 4 * HALF + 2 * Ma;  // double-buffered exchanges
   static_assert(Mb == Ma || Mb == 2 * Ma, "square or 1:2 four-step split");
 };
 
@@ -86,9 +87,30 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 }
 
 // Occupancy target (waves per SIMD) that bounds the register budget.
-template <int M>
+#ifndef GRAPHIC_COL_WAVES_1024
+#define GRAPHIC_COL_WAVES_1024 2
+#endif
+#ifndef GRAPHIC_COL_JOBS_1024
+#define GRAPHIC_COL_JOBS_1024 8
+#endif
+#ifndef GRAPHIC_COL_WAVE_LAYOUT
+#define GRAPHIC_COL_WAVE_LAYOUT 0
+#endif
+
+// Thread layout of a pass.  Row passes, and column passes when
+// GRAPHIC_COL_WAVE_LAYOUT is set, keep every job inside one wave (lanes =
+// positions of the job), so exchanges need only wave-level ordering.  The
+// default column layout puts consecutive jobs (adjacent columns) on
+// consecutive lanes, which makes every load and store a contiguous row
+// segment, at the price of block-wide barriers.
+template <int KIND>
+constexpr bool lanes_on_jobs() {
+  return KIND == kColPass && !GRAPHIC_COL_WAVE_LAYOUT;
+}
+
+template <int M, int KIND>
 constexpr int waves_per_eu() {
-  return M <= 256 ? 4 : (M == 1024 ? 3 : 2);
+  return M <= 256 ? 4 : (M == 1024 ? (lanes_on_jobs<KIND>() ? GRAPHIC_COL_WAVES_1024 : 3) : 2);
 }
 
 typedef int v2i __attribute__((ext_vector_type(2)));
@@ -111,17 +133,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, un
 constexpr unsigned kOOB = 0x80000000u;   // beyond every frame: reads 0, writes dropped
 
 // One block of jobs: frame f, jobs [jb*G, jb*G + G) of that frame.
-template <int M, int KIND, int G, int IO>
+template <int M, int KIND, int G, int IO, bool SUB>
 __device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
+  // Column blocks span several waves: their exchanges use separate buffers
+  // for real and imaginary parts, so each exchange needs one barrier.  Row
+  // blocks are one wave (barriers are free, LDS bounds occupancy): one buffer.
+  constexpr bool LJ = lanes_on_jobs<KIND>();
+  constexpr bool DB = LJ;
+  constexpr int BUF = G * 2 * S::HALF;
   extern __shared__ float lds_raw[];
   float* lds = lds_raw;
-  cf* ptab = reinterpret_cast<cf*>(lds_raw + G * 2 * S::HALF);
+  cf* ptab = reinterpret_cast<cf*>(lds_raw + BUF * (DB ? 2 : 1));
 
   const int tid = threadIdx.x;
   int jl, r;
-  if constexpr (KIND == kRowPass) {
+  if constexpr (!LJ) {
     jl = tid / JOB;
     r = tid % JOB;
   } else {
@@ -135,16 +163,27 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // keeps the job index fastest so that lanes of one wave (consecutive jobs)
   // hit consecutive words.
   auto lidx = [&](int hh, int k2, int c) -> int {
-    if constexpr (KIND == kRowPass)
+    if constexpr (!LJ)
       return (jl * 2 + hh) * S::HALF + k2 * S::ROWP + c;
     else
       return ((hh * Mb + k2) * S::ROWP + c) * G + jl;
   };
   auto tidx = [&](int k1) -> int {
-    if constexpr (KIND == kRowPass)
+    if constexpr (!LJ)
       return jl * Ma + k1;
     else
       return k1 * G + jl;
+  };
+  // exchange ordering: a block barrier when jobs span waves, otherwise only a
+  // wave-level ordering point (LDS operations of one wave complete in order)
+  auto xsync = [&]() {
+    if constexpr (LJ) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   };
 
   const int j = (int)jb * G + jl;
@@ -193,7 +232,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int ps4 = p.src_ps * 4;
   const unsigned base_a = a_ok ? (unsigned)lia * ls4 : kOOB;
   const unsigned base_b = b_ok ? (unsigned)lib * ls4 : kOOB;
-  const bool has_sub = p.sub != nullptr;
+  constexpr bool has_sub = SUB;   // subtract p.sub (the reference PSF) from every source value
   // the canonical geometries (P = 2N, frame not half-turned) use static
   // index patterns; everything else takes the general path
   constexpr bool fast = IO != kIoGeneric;
@@ -275,20 +314,30 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // ---- exchange 1 (real parts, then imaginary parts) ----
   constexpr int NQ = Mb / Ma;
   cf wv[NQ][Ma];
-#pragma unroll
-  for (int part = 0; part < 2; ++part) {
-    if (part) __syncthreads();
-#pragma unroll
-    for (int k2 = 0; k2 < Mb; ++k2) lds[lidx(h, k2, n1)] = part ? v[k2].y : v[k2].x;
-    __syncthreads();
+  auto ex1_read = [&](int part) {
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
       for (int c1 = 0; c1 < Ma; ++c1) {
-        const float t = lds[lidx(h, n1 + Ma * qq, c1)];
+        const float t = lds[(DB ? part * BUF : 0) + lidx(h, n1 + Ma * qq, c1)];
         if (part) wv[qq][c1].y = t;
         else wv[qq][c1].x = t;
       }
+  };
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (!DB && part) xsync();
+#pragma unroll
+    for (int k2 = 0; k2 < Mb; ++k2) lds[(DB ? part * BUF : 0) + lidx(h, k2, n1)] = part ? v[k2].y : v[k2].x;
+    if constexpr (!DB) {
+      xsync();
+      ex1_read(part);
+    }
+  }
+  if constexpr (DB) {
+    xsync();
+    ex1_read(0);
+    ex1_read(1);
   }
 
   // ---- step C: length-Ma transforms over n1, phasor, inverse, twiddle ----
@@ -311,20 +360,31 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   }
 
   // ---- exchange 2 ----
-#pragma unroll
-  for (int part = 0; part < 2; ++part) {
-    __syncthreads();
-#pragma unroll
-    for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-      for (int c1 = 0; c1 < Ma; ++c1) lds[lidx(h, n1 + Ma * qq, c1)] = part ? wv[qq][c1].y : wv[qq][c1].x;
-    __syncthreads();
+  auto ex2_read = [&](int part) {
 #pragma unroll
     for (int k2 = 0; k2 < Mb; ++k2) {
-      const float t = lds[lidx(h, k2, n1)];
+      const float t = lds[(DB ? part * BUF : 0) + lidx(h, k2, n1)];
       if (part) v[k2].y = t;
       else v[k2].x = t;
     }
+  };
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (!DB || part == 0) xsync();
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+      for (int c1 = 0; c1 < Ma; ++c1)
+        lds[(DB ? part * BUF : 0) + lidx(h, n1 + Ma * qq, c1)] = part ? wv[qq][c1].y : wv[qq][c1].x;
+    if constexpr (!DB) {
+      xsync();
+      ex2_read(part);
+    }
+  }
+  if constexpr (DB) {
+    xsync();
+    ex2_read(0);
+    ex2_read(1);
   }
 
   // ---- step A': length-Mb inverse transforms over k2 ----
@@ -342,12 +402,23 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int dps4 = p.dst_ps * 4;
   const unsigned obase_a = a_ok ? (unsigned)((la - dst_lo + P) & (P - 1)) * dls4 : kOOB;
   const unsigned obase_b = b_ok ? (unsigned)((lb2 - dst_lo + P) & (P - 1)) * dls4 : kOOB;
+  if constexpr (DB) {
+    xsync();
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int n2 = 0; n2 < Mb; ++n2) lds[part * BUF + lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
+    xsync();
+  }
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
-    __syncthreads();
+    if constexpr (!DB) {
+      xsync();
 #pragma unroll
-    for (int n2 = 0; n2 < Mb; ++n2) lds[lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
-    __syncthreads();
+      for (int n2 = 0; n2 < Mb; ++n2) lds[lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
+      xsync();
+    }
+    const int pb = DB ? part * BUF : 0;
     const unsigned obase = part ? obase_b : obase_a;
     if constexpr (fast && (IO == kIoWinWin || IO == kIoFullWin)) {
       // window [M/2, 3M/2): half h writes n2 >= Mb/2 (h = 0) or n2 < Mb/2 (h = 1),
@@ -356,7 +427,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const unsigned lane = obase + (unsigned)((rv ? (Ma - 1 - n1) : n1) * dps4);
 #pragma unroll
       for (int n2 = 0; n2 < Mb; ++n2) {
-        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[pb + lidx(1 - h, n2, n1)]);
         const int k = (n2 + Mb / 2) % Mb;
         const bool mine = (n2 >= Mb / 2) == (h == 0);
         buf_st(dst, mine ? lane : kOOB, y, (rv ? Ma * (Mb - 1 - k) : Ma * k) * dps4);
@@ -368,13 +439,13 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
           obase + (unsigned)((rv ? (Ma - 1 - n1) + (1 - h) * M : n1 + h * M) * dps4);
 #pragma unroll
       for (int n2 = 0; n2 < Mb; ++n2) {
-        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[pb + lidx(1 - h, n2, n1)]);
         buf_st(dst, lane, y, (rv ? Ma * (Mb - 1 - n2) : Ma * n2) * dps4);
       }
     } else {
 #pragma unroll
       for (int n2 = 0; n2 < Mb; ++n2) {
-        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[lidx(1 - h, n2, n1)]);
+        const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[pb + lidx(1 - h, n2, n1)]);
         const int n = n1 + Ma * n2 + h * M;
         const int pos = (part && p.mirror) ? ((R - n) % P + P) % P : n;
         const int u = pos - p.out_off;
@@ -390,29 +461,39 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
 // the pass reads half-turned frames through a different support (first shear
 // and column shear of a rotation), those frames are skipped here and handled
 // by line_pass_flipped_kernel.
-template <int M, int KIND, int G, int IO>
-__global__ void __launch_bounds__(G * Shape<M>::JOB, waves_per_eu<M>())
+template <int M, int KIND, int G, int IO, bool SUB>
+__global__ void __launch_bounds__(G * Shape<M>::JOB)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND>(), waves_per_eu<M, KIND>())))
 line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
   const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  const unsigned f = lb / (unsigned)p.blocks_per_frame;
-  const unsigned jb = lb - f * (unsigned)p.blocks_per_frame;
+  // Passes that subtract the reference frame walk jobs in job-major order:
+  // with the XCD remap each XCD then reads only its own slice of the
+  // reference frame's lines, which stays in its L2.
+  unsigned f, jb;
+  if constexpr (SUB) {
+    jb = lb / (unsigned)p.n_frames;
+    f = lb - jb * (unsigned)p.n_frames;
+  } else {
+    f = lb / (unsigned)p.blocks_per_frame;
+    jb = lb - f * (unsigned)p.blocks_per_frame;
+  }
   if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
     return;   // whole block leaves together, before any barrier
-  process_block<M, KIND, G, IO>(p, f, jb);
+  process_block<M, KIND, G, IO, SUB>(p, f, jb);
 }
 
 // General path for the half-turned frames listed in p.flip_list (count in
 // p.flip_count): a fixed grid walks the (frame, block) pairs.
-template <int M, int KIND, int G>
-__global__ void __launch_bounds__(G * Shape<M>::JOB, waves_per_eu<M>())
+template <int M, int KIND, int G, bool SUB>
+__global__ void __launch_bounds__(G * Shape<M>::JOB, (waves_per_eu<M, KIND>()))
 line_pass_flipped_kernel(const LinePass p) {
   const unsigned bpf = (unsigned)p.blocks_per_frame;
   const unsigned work = (unsigned)(*p.flip_count) * bpf;
   for (unsigned w = blockIdx.x; w < work; w += gridDim.x) {
     const unsigned f = (unsigned)p.flip_list[w / bpf];
-    process_block<M, KIND, G, kIoGeneric>(p, f, w % bpf);
+    process_block<M, KIND, G, kIoGeneric, SUB>(p, f, w % bpf);
     __syncthreads();
   }
 }
@@ -424,9 +505,11 @@ line_pass_flipped_kernel(const LinePass p) {
 template <int M>
 constexpr int col_jobs_per_block() {
   using S = Shape<M>;
-  constexpr int budget = 80 * 1024;
+  if (M == 1024) return GRAPHIC_COL_JOBS_1024;
+  if (!lanes_on_jobs<kColPass>()) return 64 / S::JOB > 0 ? 64 / S::JOB : 1;
+  constexpr int budget = 140 * 1024;
   int g = 16;
-  while (g > 1 && (g * S::PER_JOB_F * 4 > budget || g * S::JOB > 1024)) g /= 2;
+  while (g > 1 && (g * S::PER_JOB_F_DB * 4 > budget || g * S::JOB > 1024)) g /= 2;
   return g;
 }
 
@@ -435,24 +518,24 @@ constexpr int row_jobs_per_block() {
   return 64 / Shape<M>::JOB > 0 ? 64 / Shape<M>::JOB : 1;
 }
 
-template <int M, int KIND, int G, int IO>
+template <int M, int KIND, int G, int IO, bool SUB>
 static hipError_t launch_g(LinePass p, hipStream_t st) {
   using S = Shape<M>;
   p.blocks_per_frame = (p.n_jobs + G - 1) / G;
   const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = (size_t)G * S::PER_JOB_F * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO>,
+  const size_t lds = (size_t)G * (lanes_on_jobs<KIND>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * sizeof(float);
+  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, SUB>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, SUB>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || IO == kIoGeneric || p.flip == nullptr || !(p.flip_in_off || p.flip_src_reverse))
     return e;
   // half-turned frames: general path over the device-side list
-  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G>,
+  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, SUB>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long fb = std::min<long long>(blocks, 2048);
-  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, SUB>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
   return hipGetLastError();
 }
 
@@ -471,13 +554,24 @@ static int io_kind(const LinePass& p) {
   return kIoGeneric;
 }
 
+// Only the first shear of a rotation (window rows in, all columns out, a row
+// pass) subtracts a reference frame.
 template <int M, int KIND, int G>
 static hipError_t launch_io(const LinePass& p, hipStream_t st) {
+  const bool sub = p.sub != nullptr;
   switch (io_kind(p)) {
-    case kIoWinWin: return launch_g<M, KIND, G, kIoWinWin>(p, st);
-    case kIoWinFull: return launch_g<M, KIND, G, kIoWinFull>(p, st);
-    case kIoFullWin: return launch_g<M, KIND, G, kIoFullWin>(p, st);
-    default: return launch_g<M, KIND, G, kIoGeneric>(p, st);
+    case kIoWinWin: return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoWinWin, false>(p, st);
+    case kIoWinFull:
+      if constexpr (KIND == kRowPass)
+        return sub ? launch_g<M, KIND, G, kIoWinFull, true>(p, st) : launch_g<M, KIND, G, kIoWinFull, false>(p, st);
+      else
+        return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoWinFull, false>(p, st);
+    case kIoFullWin: return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoFullWin, false>(p, st);
+    default:
+      if constexpr (KIND == kRowPass)
+        return sub ? launch_g<M, KIND, G, kIoGeneric, true>(p, st) : launch_g<M, KIND, G, kIoGeneric, false>(p, st);
+      else
+        return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoGeneric, false>(p, st);
   }
 }
 

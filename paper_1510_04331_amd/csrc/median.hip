@@ -18,13 +18,15 @@
 
 #include "internal.h"
 
+#ifndef GRAPHIC_MEDIAN_PIX
+#define GRAPHIC_MEDIAN_PIX 16
+#endif
+
 namespace graphic {
 
 namespace {
 
-constexpr int kPix = 16;          // pixels per block
 constexpr int kGroups = 64;       // frame groups (threads) per pixel
-constexpr int kThreads = kPix * kGroups;
 constexpr int kBins = 256;
 constexpr int kHistPitch = kBins + 1;   // +1 word: pixels land on distinct banks
 
@@ -37,17 +39,23 @@ __device__ __forceinline__ float val_of(unsigned k) {
   return __uint_as_float(b);
 }
 
-template <int VPT>
-__global__ void __launch_bounds__(kThreads) median_kernel(const float* __restrict__ stack, long long T,
-                                                          long long npix, float* __restrict__ out) {
+// kPix pixels per block (one wave per pixel for the histogram scans).  With
+// resid != nullptr every value is also written back as value - median
+// (in place is allowed: each thread rewrites exactly the values it read).
+template <int VPT, int kPix>
+__global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __restrict__ stack, long long T,
+                                                                long long npix, float* __restrict__ out,
+                                                                float* resid) {
+  constexpr int kThreads = kPix * kGroups;
   __shared__ unsigned hist[kPix * kHistPitch];
   __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix];
+  __shared__ float sel_med[kPix];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int px = lane & (kPix - 1);
-  const int g = (lane >> 4) + 4 * wave;          // frame group 0..63
+  const int px = lane % kPix;
+  const int g = lane / kPix + (64 / kPix) * wave;   // frame group 0..63
   const long long pix = (long long)blockIdx.x * kPix + px;
   const bool pix_ok = pix < npix;
 
@@ -127,24 +135,38 @@ __global__ void __launch_bounds__(kThreads) median_kernel(const float* __restric
   atomicMin(&sel_min[px], local_min);
   __syncthreads();
 
-  if (pix_ok && g == 0) {
+  if (g == 0) {
     const unsigned step = (unsigned)(T / 2) - k_lo;      // 0 (odd T) or 1
     const float lo = val_of(lo_key);
     const float hi = (sel_rank[px] + step < sel_cnt[px]) ? lo : val_of(sel_min[px]);
-    out[pix] = (lo + hi) * 0.5f;
+    const float med = (lo + hi) * 0.5f;
+    sel_med[px] = med;
+    if (pix_ok) out[pix] = med;
+  }
+  if (resid != nullptr) {
+    __syncthreads();
+    const float med = sel_med[px];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const long long t = g + (long long)kGroups * i;
+      if (pix_ok && t < T) resid[t * npix + pix] = val_of(key[i]) - med;
+    }
   }
 }
 
 }  // namespace
 
-hipError_t launch_median(const float* stack, long long T, long long npix, float* out, hipStream_t s) {
+hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
+                         hipStream_t s) {
   if (T <= 0 || npix <= 0) return hipSuccess;
   const long long vpt = (T + kGroups - 1) / kGroups;
-  const unsigned blocks = (unsigned)((npix + kPix - 1) / kPix);
-#define GRAPHIC_MEDIAN_CASE(V)                                                                     \
-  if (vpt <= V) {                                                                                 \
-    hipLaunchKernelGGL((median_kernel<V>), dim3(blocks), dim3(kThreads), 0, s, stack, T, npix, out); \
-    return hipGetLastError();                                                                     \
+  constexpr int PIX = GRAPHIC_MEDIAN_PIX;
+  const unsigned blocks = (unsigned)((npix + PIX - 1) / PIX);
+#define GRAPHIC_MEDIAN_CASE(V)                                                                         \
+  if (vpt <= V) {                                                                                     \
+    hipLaunchKernelGGL((median_kernel<V, PIX>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, npix, out, \
+                       resid);                                                                        \
+    return hipGetLastError();                                                                         \
   }
   GRAPHIC_MEDIAN_CASE(1)
   GRAPHIC_MEDIAN_CASE(2)
