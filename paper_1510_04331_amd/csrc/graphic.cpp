@@ -8,9 +8,9 @@
 //   rotate (Sect. 3.4):    x-shear of every window row into a N x P scratch
 //                          frame, y-shear of every scratch column (in place),
 //                          x-shear of every window row into out.
-//   adi    (Sect. 3):      shift -> median PSF -> rotate(S - PSF, -parang)
-//                          with the subtraction fused into the first shear ->
-//                          median.
+//   adi    (Sect. 3):      shift -> median PSF (which also rewrites the stack
+//                          as residuals S - PSF) -> rotate(residuals, -parang)
+//                          -> median.
 
 #include "../../include/graphic.h"
 
@@ -249,10 +249,8 @@ graphic_status do_shift(graphic_ctx ctx, long long T, int N, int P, const float*
   return run_pass(ctx, r, kRowPass, "shift_x", st);
 }
 
-// Rotation of frames [0, T) of `src` into `dst` (may alias src), optionally
-// subtracting `sub` (N x N) from every source frame first.
-graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float* src, const float* sub,
-                         float* dst, const double* theta, double sign, void* ws, size_t ws_bytes,
+// Rotation of frames [0, T) of `src` into `dst` (may alias src).
+graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float* src, float* dst, const double* theta, double sign, void* ws, size_t ws_bytes,
                          hipStream_t st) {
   RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, ws_bytes);
   if (L.chunk_frames < 1) return GRAPHIC_ERR_WORKSPACE;
@@ -281,13 +279,11 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     // x-shear 1: window rows -> all P columns of the scratch frame
     LinePass a = base_pass(ctx, P);
     a.src = src + f0 * (long long)N * N;
-    a.sub = sub;
     a.dst = scratch;
     a.src_fs = (long long)N * N;
     a.dst_fs = (long long)N * P;
     a.src_ls = N;
     a.src_ps = 1;
-    a.sub_bytes = sub ? (long long)N * N * 4 : 0;   // same (row, column) strides as the source
     a.dst_ls = P;
     a.dst_ps = 1;
     a.line_lo = o;
@@ -495,7 +491,7 @@ graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom, const f
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
   if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
-  if ((s = do_rotate(ctx, T, N, P, in, nullptr, out, theta_deg, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
+  if ((s = do_rotate(ctx, T, N, P, in, out, theta_deg, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
   if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
 }
@@ -552,7 +548,7 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, con
   // the PSF median also rewrites the stack as residuals S_i - PSF (Sect. 3.3),
   // so the rotation reads them directly
   if ((s = do_median(ctx, T, N, stack, psf_buf, stack, st)) != GRAPHIC_OK) return s;
-  if ((s = do_rotate(ctx, T, N, P, stack, nullptr, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
+  if ((s = do_rotate(ctx, T, N, P, stack, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
     return s;
   return do_median(ctx, T, N, stack, final_img, nullptr, st);
 }

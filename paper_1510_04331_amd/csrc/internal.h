@@ -28,9 +28,6 @@ struct LinePass {
   // memory: element (frame f, line li, position pi) at base + f*fs + li*ls + pi*ps
   const float* src;
   float* dst;
-  const float* sub;       // nullable N x N frame subtracted from every source value;
-                          // indexed with the source's own (line, position) strides
-  long long sub_bytes;
   long long src_fs, dst_fs;
   int src_ls, src_ps, dst_ls, dst_ps;
 

@@ -133,7 +133,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, un
 constexpr unsigned kOOB = 0x80000000u;   // beyond every frame: reads 0, writes dropped
 
 // One block of jobs: frame f, jobs [jb*G, jb*G + G) of that frame.
-template <int M, int KIND, int G, int IO, bool SUB>
+template <int M, int KIND, int G, int IO, bool MIR>
 __device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
@@ -197,7 +197,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // support wraps, and padded line P is line 0 (shift -c * coef).
   int la, lb2;
   bool b_exists = true;
-  if (p.mirror) {
+  if (MIR) {
     la = c - j;                     // j in [0, c]
     lb2 = (c + j) & (P - 1);
     b_exists = (j != 0) && (lb2 != la);
@@ -218,12 +218,11 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int L = p.in_len;
   const int R = 2 * in_off + L - 1;
   const bool rev = p.flip_src_reverse && flipf;
-  const bool rev_b = p.mirror ? !rev : rev;
+  const bool rev_b = MIR ? !rev : rev;
   const int lia = rev ? (p.n_lines - 1 - ra) : ra;
   const int lib = rev ? (p.n_lines - 1 - rb) : rb;
 
   const __amdgpu_buffer_rsrc_t src = make_rsrc(p.src + (size_t)f * p.src_fs, (unsigned)p.src_fs * 4u);
-  const __amdgpu_buffer_rsrc_t sub = make_rsrc(p.sub, p.sub ? (unsigned)p.sub_bytes : 0u);
   const __amdgpu_buffer_rsrc_t dst = make_rsrc(p.dst + (size_t)f * p.dst_fs, (unsigned)p.dst_fs * 4u);
   const __amdgpu_buffer_rsrc_t tfold = make_rsrc(p.tw.fold, 2u * M * 8u);
   const __amdgpu_buffer_rsrc_t tfwd = make_rsrc(p.tw.fwd, (unsigned)M * 8u);
@@ -232,7 +231,6 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int ps4 = p.src_ps * 4;
   const unsigned base_a = a_ok ? (unsigned)lia * ls4 : kOOB;
   const unsigned base_b = b_ok ? (unsigned)lib * ls4 : kOOB;
-  constexpr bool has_sub = SUB;   // subtract p.sub (the reference PSF) from every source value
   // the canonical geometries (P = 2N, frame not half-turned) use static
   // index patterns; everything else takes the general path
   constexpr bool fast = IO != kIoGeneric;
@@ -251,17 +249,13 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     // support [M/2, 3M/2): element m = n1 + Ma n2 has exactly one valid
     // candidate, position u = n1 + Ma ((n2 + Mb/2) mod Mb) of the source line
     const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
-    const unsigned lb_lane = base_b + (unsigned)((p.mirror ? (Ma - 1 - n1) : n1) * ps4);
+    const unsigned lb_lane = base_b + (unsigned)((MIR ? (Ma - 1 - n1) : n1) * ps4);
 #pragma unroll
     for (int n2 = 0; n2 < Mb; ++n2) {
       const int k = (n2 + Mb / 2) % Mb;
       const int sa = Ma * k * ps4;
-      const int sb = (p.mirror ? Ma * (Mb - 1 - k) : Ma * k) * ps4;
-      float av = buf_ld(src, la_lane, sa), bv = buf_ld(src, lb_lane, sb);
-      if (has_sub) {
-        av -= buf_ld(sub, la_lane, sa);
-        bv -= buf_ld(sub, lb_lane, sb);
-      }
+      const int sb = (MIR ? Ma * (Mb - 1 - k) : Ma * k) * ps4;
+      const float av = buf_ld(src, la_lane, sa), bv = buf_ld(src, lb_lane, sb);
       const float sc = n2 < Mb / 2 ? sg : 1.0f;    // the valid candidate is n = m + M below Mb/2
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({sc * av, sc * bv}, w);
@@ -269,12 +263,12 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   } else if constexpr (fast && IO == kIoFullWin) {
     // support [0, P): both candidates n = m and n = m + M are valid
     const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
-    const unsigned lb_lane = base_b + (unsigned)((p.mirror ? (Ma - 1 - n1) : n1) * ps4);
+    const unsigned lb_lane = base_b + (unsigned)((MIR ? (Ma - 1 - n1) : n1) * ps4);
 #pragma unroll
     for (int n2 = 0; n2 < Mb; ++n2) {
       const int sa0 = Ma * n2 * ps4, sa1 = (Ma * n2 + M) * ps4;
-      const int sb0 = (p.mirror ? Ma * (2 * Mb - 1 - n2) : Ma * n2) * ps4;
-      const int sb1 = (p.mirror ? Ma * (Mb - 1 - n2) : Ma * n2 + M) * ps4;
+      const int sb0 = (MIR ? Ma * (2 * Mb - 1 - n2) : Ma * n2) * ps4;
+      const int sb1 = (MIR ? Ma * (Mb - 1 - n2) : Ma * n2 + M) * ps4;
       const float a0 = buf_ld(src, la_lane, sa0), a1 = buf_ld(src, la_lane, sa1);
       const float b0 = buf_ld(src, lb_lane, sb0), b1 = buf_ld(src, lb_lane, sb1);
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
@@ -294,12 +288,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
         const unsigned pb = (unsigned)(rev_b ? (L - 1 - u) : u);
         const unsigned oa = in ? base_a + pa * (unsigned)ps4 : kOOB;
         const unsigned ob = in ? base_b + pb * (unsigned)ps4 : kOOB;
-        float av = buf_ld(src, oa), bv = buf_ld(src, ob);
-        if (has_sub) {
-          av -= buf_ld(sub, oa);
-          bv -= buf_ld(sub, ob);
-        }
-        z[cnd] = {av, bv};
+        z[cnd] = {buf_ld(src, oa), buf_ld(src, ob)};
       }
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
@@ -423,7 +412,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     if constexpr (fast && (IO == kIoWinWin || IO == kIoFullWin)) {
       // window [M/2, 3M/2): half h writes n2 >= Mb/2 (h = 0) or n2 < Mb/2 (h = 1),
       // at window position n1 + Ma ((n2 + Mb/2) mod Mb) (reversed for line b')
-      const bool rv = part && p.mirror;
+      const bool rv = part && MIR;
       const unsigned lane = obase + (unsigned)((rv ? (Ma - 1 - n1) : n1) * dps4);
 #pragma unroll
       for (int n2 = 0; n2 < Mb; ++n2) {
@@ -434,7 +423,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       }
     } else if constexpr (fast && IO == kIoWinFull) {
       // all P positions: n = m + h M (reversed, P - 1 - n, for line b')
-      const bool rv = part && p.mirror;
+      const bool rv = part && MIR;
       const unsigned lane =
           obase + (unsigned)((rv ? (Ma - 1 - n1) + (1 - h) * M : n1 + h * M) * dps4);
 #pragma unroll
@@ -447,7 +436,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       for (int n2 = 0; n2 < Mb; ++n2) {
         const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[pb + lidx(1 - h, n2, n1)]);
         const int n = n1 + Ma * n2 + h * M;
-        const int pos = (part && p.mirror) ? ((R - n) % P + P) % P : n;
+        const int pos = (part && MIR) ? ((R - n) % P + P) % P : n;
         const int u = pos - p.out_off;
         buf_st(dst, (u >= 0 && u < p.out_len) ? obase + (unsigned)(u * dps4) : kOOB, y);
       }
@@ -461,39 +450,30 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
 // the pass reads half-turned frames through a different support (first shear
 // and column shear of a rotation), those frames are skipped here and handled
 // by line_pass_flipped_kernel.
-template <int M, int KIND, int G, int IO, bool SUB>
+template <int M, int KIND, int G, int IO, bool MIR>
 __global__ void __launch_bounds__(G * Shape<M>::JOB)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND>(), waves_per_eu<M, KIND>())))
 line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
   const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  // Passes that subtract the reference frame walk jobs in job-major order:
-  // with the XCD remap each XCD then reads only its own slice of the
-  // reference frame's lines, which stays in its L2.
-  unsigned f, jb;
-  if constexpr (SUB) {
-    jb = lb / (unsigned)p.n_frames;
-    f = lb - jb * (unsigned)p.n_frames;
-  } else {
-    f = lb / (unsigned)p.blocks_per_frame;
-    jb = lb - f * (unsigned)p.blocks_per_frame;
-  }
+  const unsigned f = lb / (unsigned)p.blocks_per_frame;
+  const unsigned jb = lb - f * (unsigned)p.blocks_per_frame;
   if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
     return;   // whole block leaves together, before any barrier
-  process_block<M, KIND, G, IO, SUB>(p, f, jb);
+  process_block<M, KIND, G, IO, MIR>(p, f, jb);
 }
 
 // General path for the half-turned frames listed in p.flip_list (count in
 // p.flip_count): a fixed grid walks the (frame, block) pairs.
-template <int M, int KIND, int G, bool SUB>
+template <int M, int KIND, int G, bool MIR>
 __global__ void __launch_bounds__(G * Shape<M>::JOB, (waves_per_eu<M, KIND>()))
 line_pass_flipped_kernel(const LinePass p) {
   const unsigned bpf = (unsigned)p.blocks_per_frame;
   const unsigned work = (unsigned)(*p.flip_count) * bpf;
   for (unsigned w = blockIdx.x; w < work; w += gridDim.x) {
     const unsigned f = (unsigned)p.flip_list[w / bpf];
-    process_block<M, KIND, G, kIoGeneric, SUB>(p, f, w % bpf);
+    process_block<M, KIND, G, kIoGeneric, MIR>(p, f, w % bpf);
     __syncthreads();
   }
 }
@@ -518,24 +498,24 @@ constexpr int row_jobs_per_block() {
   return 64 / Shape<M>::JOB > 0 ? 64 / Shape<M>::JOB : 1;
 }
 
-template <int M, int KIND, int G, int IO, bool SUB>
+template <int M, int KIND, int G, int IO, bool MIR>
 static hipError_t launch_g(LinePass p, hipStream_t st) {
   using S = Shape<M>;
   p.blocks_per_frame = (p.n_jobs + G - 1) / G;
   const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const size_t lds = (size_t)G * (lanes_on_jobs<KIND>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, SUB>,
+  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, SUB>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || IO == kIoGeneric || p.flip == nullptr || !(p.flip_in_off || p.flip_src_reverse))
     return e;
   // half-turned frames: general path over the device-side list
-  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, SUB>,
+  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, MIR>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const long long fb = std::min<long long>(blocks, 2048);
-  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, SUB>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
   return hipGetLastError();
 }
 
@@ -554,25 +534,26 @@ static int io_kind(const LinePass& p) {
   return kIoGeneric;
 }
 
-// Only the first shear of a rotation (window rows in, all columns out, a row
-// pass) subtracts a reference frame.
+// Instantiations that the operations use: the shift passes pair adjacent
+// lines, the rotation passes pair mirrored lines.
 template <int M, int KIND, int G>
 static hipError_t launch_io(const LinePass& p, hipStream_t st) {
-  const bool sub = p.sub != nullptr;
-  switch (io_kind(p)) {
-    case kIoWinWin: return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoWinWin, false>(p, st);
-    case kIoWinFull:
-      if constexpr (KIND == kRowPass)
-        return sub ? launch_g<M, KIND, G, kIoWinFull, true>(p, st) : launch_g<M, KIND, G, kIoWinFull, false>(p, st);
-      else
-        return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoWinFull, false>(p, st);
-    case kIoFullWin: return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoFullWin, false>(p, st);
-    default:
-      if constexpr (KIND == kRowPass)
-        return sub ? launch_g<M, KIND, G, kIoGeneric, true>(p, st) : launch_g<M, KIND, G, kIoGeneric, false>(p, st);
-      else
-        return sub ? hipErrorInvalidValue : launch_g<M, KIND, G, kIoGeneric, false>(p, st);
+  const int io = io_kind(p);
+  if (!p.mirror) {
+    if (io == kIoWinWin) return launch_g<M, KIND, G, kIoWinWin, false>(p, st);
+    return launch_g<M, KIND, G, kIoGeneric, false>(p, st);
   }
+  switch (io) {
+    case kIoWinWin: return launch_g<M, KIND, G, kIoWinWin, true>(p, st);
+    case kIoWinFull:
+      if constexpr (KIND == kRowPass) return launch_g<M, KIND, G, kIoWinFull, true>(p, st);
+      break;
+    case kIoFullWin:
+      if constexpr (KIND == kRowPass) return launch_g<M, KIND, G, kIoFullWin, true>(p, st);
+      break;
+    default: break;
+  }
+  return launch_g<M, KIND, G, kIoGeneric, true>(p, st);
 }
 
 template <int M>

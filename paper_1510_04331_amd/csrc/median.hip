@@ -42,7 +42,23 @@ __device__ __forceinline__ float val_of(unsigned k) {
 // kPix pixels per block (one wave per pixel for the histogram scans).  With
 // resid != nullptr every value is also written back as value - median
 // (in place is allowed: each thread rewrites exactly the values it read).
-template <int VPT, int kPix>
+// Inclusive prefix sum over the 64 lanes of a wave with DPP: four row_shr
+// steps scan each row of 16 lanes, two row_bcast steps carry across rows.
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned x) {
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frames_rsrc(const float* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int VPT, int kPix, bool BUF>
 __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __restrict__ stack, long long T,
                                                                 long long npix, float* __restrict__ out,
                                                                 float* resid) {
@@ -59,12 +75,29 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   const long long pix = (long long)blockIdx.x * kPix + px;
   const bool pix_ok = pix < npix;
 
+  // Frames 64 i .. 64 i + 63 form group i; one wave-uniform buffer descriptor
+  // per group keeps the per-lane address a single 32-bit offset
+  // (g * npix + pix) * 4, and offsets past the group's frames read 0.
+  const long long pix0 = (long long)blockIdx.x * kPix;
+  const unsigned voff = pix_ok ? (unsigned)(((long long)g * npix + (pix - pix0)) * 4) : 0x80000000u;
+  auto group = [&](int i) {
+    const long long f0 = (long long)kGroups * i;
+    const long long nf = T - f0 < kGroups ? T - f0 : kGroups;
+    const long long bytes = nf > 0 ? (nf - 1) * npix * 4 + (npix - pix0) * 4 : 0;
+    return frames_rsrc(stack + f0 * npix + pix0, (unsigned)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL));
+  };
   unsigned key[VPT];
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
     const long long t = g + (long long)kGroups * i;
-    key[i] = 0xFFFFFFFFu;   // padding sorts after every real (non-NaN) value
-    if (pix_ok && t < T) key[i] = key_of(stack[t * npix + pix]);
+    const bool valid = t < T;
+    float v;
+    if constexpr (BUF) {
+      v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(group(i), (int)voff, 0, 0));
+    } else {
+      v = (valid && pix_ok) ? stack[t * npix + pix] : 0.0f;   // frames too large for 32-bit offsets
+    }
+    key[i] = valid ? key_of(v) : 0xFFFFFFFFu;   // padding sorts after every real (non-NaN) value
   }
 
   const unsigned k_lo = (unsigned)((T - 1) / 2);
@@ -95,19 +128,14 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk) {
         const unsigned x = hist[w * kHistPitch + blk * 64 + lane];
-        unsigned incl = x;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const unsigned y = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += y;
-        }
-        const unsigned tot = __shfl(incl, 63, 64);
+        const unsigned incl = wave_incl_scan(x);
+        const unsigned tot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
         const unsigned long long hit = __ballot(carry + incl > k);
         if (found_bin < 0 && hit != 0ull) {
           const int l0 = __ffsll((long long)hit) - 1;
           found_bin = blk * 64 + l0;
-          const unsigned incl0 = __shfl(incl, l0, 64);
-          const unsigned x0 = __shfl(x, l0, 64);
+          const unsigned incl0 = (unsigned)__builtin_amdgcn_readlane((int)incl, l0);
+          const unsigned x0 = (unsigned)__builtin_amdgcn_readlane((int)x, l0);
           below = carry + incl0 - x0;
           inbin = x0;
         }
@@ -146,10 +174,20 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   if (resid != nullptr) {
     __syncthreads();
     const float med = sel_med[px];
+    const float* rbase = resid;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const long long t = g + (long long)kGroups * i;
-      if (pix_ok && t < T) resid[t * npix + pix] = val_of(key[i]) - med;
+      const long long f0 = (long long)kGroups * i;
+      if constexpr (BUF) {
+        const long long nf = T - f0 < kGroups ? T - f0 : kGroups;
+        const long long bytes = nf > 0 ? (nf - 1) * npix * 4 + (npix - pix0) * 4 : 0;
+        const __amdgpu_buffer_rsrc_t r =
+            frames_rsrc(rbase + f0 * npix + pix0, (unsigned)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL));
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), r, (int)voff, 0, 0);
+      } else {
+        const long long t = g + f0;
+        if (pix_ok && t < T) resid[t * npix + pix] = val_of(key[i]) - med;
+      }
     }
   }
 }
@@ -162,11 +200,17 @@ hipError_t launch_median(const float* stack, long long T, long long npix, float*
   const long long vpt = (T + kGroups - 1) / kGroups;
   constexpr int PIX = GRAPHIC_MEDIAN_PIX;
   const unsigned blocks = (unsigned)((npix + PIX - 1) / PIX);
-#define GRAPHIC_MEDIAN_CASE(V)                                                                         \
-  if (vpt <= V) {                                                                                     \
-    hipLaunchKernelGGL((median_kernel<V, PIX>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, npix, out, \
-                       resid);                                                                        \
-    return hipGetLastError();                                                                         \
+  // 32-bit buffer offsets cover 64 frames of the stack when 64 * npix * 4 < 2^31
+  const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
+#define GRAPHIC_MEDIAN_CASE(V)                                                                            \
+  if (vpt <= V) {                                                                                        \
+    if (buf)                                                                                             \
+      hipLaunchKernelGGL((median_kernel<V, PIX, true>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, \
+                         npix, out, resid);                                                              \
+    else                                                                                                 \
+      hipLaunchKernelGGL((median_kernel<V, PIX, false>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, \
+                         npix, out, resid);                                                              \
+    return hipGetLastError();                                                                            \
   }
   GRAPHIC_MEDIAN_CASE(1)
   GRAPHIC_MEDIAN_CASE(2)
