@@ -170,6 +170,43 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
                                   float* psf, float* residuals,
                                   void* ws, size_t ws_bytes, graphic_stream stream);
 
+/*
+ * Batched ADI reduction of cubes of uneven frame count and size (the
+ * classical reduction of graphic_adi_reduce applied to every cube).  Cubes
+ * with the same N and P form a size class; every line pass of a class runs
+ * over the frames of up to 16 of its cubes in one launch, and the rotation
+ * works through the concatenated frames of the class in chunks that may span
+ * cubes.  The results are bitwise identical to one graphic_adi_reduce call
+ * per cube.  Each cube is described by a graphic_cube_desc (host array,
+ * device pointers).
+ *   flags : 0, or GRAPHIC_BATCH_INPLACE to use each cube's input array as its
+ *           working stack (the input is overwritten with the derotated
+ *           residuals); otherwise the stack goes to `residuals` if given, or
+ *           to the workspace.
+ *   ws    : graphic_batch_workspace_size() bytes; a smaller workspace (down
+ *           to the stacks, PSFs and one working frame) makes the rotation
+ *           use smaller chunks.
+ */
+#define GRAPHIC_BATCH_INPLACE 1u
+
+typedef struct {
+    const float* cube;          /* [T][N][N] float32 */
+    int64_t n_frames;           /* T, 1 <= T <= 4096 */
+    int32_t n, pad;             /* N and P as in graphic_geom */
+    const double* dx;           /* [T] recentring shifts */
+    const double* dy;           /* [T] */
+    const double* parang_deg;   /* [T] parallactic angles; frames are derotated by -parang */
+    float* final_img;           /* [N][N] output */
+    float* psf;                 /* NULL or [N][N] output */
+    float* residuals;           /* NULL or [T][N][N] output (derotated residuals) */
+} graphic_cube_desc;
+
+graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                            uint32_t flags, size_t* bytes);
+
+graphic_status graphic_adi_reduce_batch(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                        uint32_t flags, void* ws, size_t ws_bytes, graphic_stream stream);
+
 /* Per-kernel timing with HIP events on the caller's stream (for benchmarks).
  * When enabled, every library kernel launch is bracketed by events; the
  * accumulated milliseconds and launch counts per kernel family are read with

@@ -4,5 +4,6 @@ The computation lives in libgraphic.so (hand-written HIP for gfx950) behind the
 C ABI of include/graphic.h; this package only marshals torch tensors to it.
 """
 
-from .ops import shift, rotate, median, adi_reduce, workspace_size, timing_enable, timing_read  # noqa: F401
+from .ops import (shift, rotate, median, adi_reduce, adi_reduce_batch, workspace_size,  # noqa: F401
+                  batch_workspace_size, timing_enable, timing_read)
 from ._abi import LIB_PATH, GraphicError  # noqa: F401

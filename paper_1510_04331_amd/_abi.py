@@ -18,13 +18,22 @@ OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN = range(4)
 EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
-    "graphic_median", "graphic_adi_reduce", "graphic_timing_enable", "graphic_timing_read",
+    "graphic_median", "graphic_adi_reduce", "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
+    "graphic_timing_enable", "graphic_timing_read",
 )
+BATCH_INPLACE = 1
 
 
 class Geom(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int64), ("n", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class CubeDesc(ctypes.Structure):
+    _fields_ = [("cube", ctypes.c_void_p), ("n_frames", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p),
+                ("parang_deg", ctypes.c_void_p), ("final_img", ctypes.c_void_p), ("psf", ctypes.c_void_p),
+                ("residuals", ctypes.c_void_p)]
 
 
 class GraphicError(RuntimeError):
@@ -68,6 +77,11 @@ def load():
     lib.graphic_median.restype = st
     lib.graphic_adi_reduce.argtypes = [vp, g, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.graphic_adi_reduce.restype = st
+    cd = ctypes.POINTER(CubeDesc)
+    lib.graphic_batch_workspace_size.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)]
+    lib.graphic_batch_workspace_size.restype = st
+    lib.graphic_adi_reduce_batch.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, vp, sz, vp]
+    lib.graphic_adi_reduce_batch.restype = st
     lib.graphic_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.graphic_timing_enable.restype = st
     lib.graphic_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),

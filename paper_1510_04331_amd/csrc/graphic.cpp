@@ -16,7 +16,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -170,14 +173,6 @@ RotLayout rot_layout(long long T, int N, int P, size_t chunk_bytes, size_t avail
 
 size_t shift_ws(long long, int, int) { return 0; }
 
-size_t adi_ws(long long T, int N, int P, size_t chunk_bytes, bool have_residuals, bool have_psf) {
-  size_t s = 0;
-  if (!have_residuals) s += align_up((size_t)T * N * N * sizeof(float));
-  if (!have_psf) s += align_up((size_t)N * N * sizeof(float));
-  s += rot_layout(T, N, P, chunk_bytes, 0).total;
-  return s;
-}
-
 // ---------------------------------------------------------------------------
 // Launch helpers (with optional event timing)
 // ---------------------------------------------------------------------------
@@ -218,67 +213,107 @@ LinePass base_pass(graphic_ctx ctx, int P) {
   return p;
 }
 
-// Shift: column pass (content moves by dy along y) then row pass (dx along x).
-graphic_status do_shift(graphic_ctx ctx, long long T, int N, int P, const float* in, float* out,
-                        const double* dx, const double* dy, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// Batched passes over one size class (every cube has the same N and P).  A
+// single-cube call is a batch of one.
+// ---------------------------------------------------------------------------
+struct ShiftItem {
+  const float* in;
+  float* out;
+  long long T;
+  const double* dx;
+  const double* dy;
+};
+
+struct RotItem {
+  const float* src;
+  float* dst;
+  long long T;
+  const double* theta;
+};
+
+// Shift (Sect. 3.3.1): column pass (content moves by dy along y) then row pass
+// (dx along x); up to kMaxCubesPerLaunch cubes per launch.
+graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it, int n, hipStream_t st) {
   const int o = (P - N) / 2;
-  LinePass c = base_pass(ctx, P);
-  c.src = in;
-  c.dst = out;
-  c.src_fs = c.dst_fs = (long long)N * N;
-  c.src_ls = c.dst_ls = 1;
-  c.src_ps = c.dst_ps = N;
-  c.line_lo = o;
-  c.n_lines = N;
-  c.in_off = o;
-  c.in_len = N;
-  c.out_off = o;
-  c.out_len = N;
-  c.dst_line_lo = o;
-  c.mirror = 0;
-  c.n_jobs = N / 2;
-  c.n_frames = T;
-  c.sh0 = dy;
-  graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
-  if (s != GRAPHIC_OK) return s;
-  LinePass r = c;
-  r.src = out;
-  r.src_ls = r.dst_ls = N;
-  r.src_ps = r.dst_ps = 1;
-  r.sh0 = dx;
-  return run_pass(ctx, r, kRowPass, "shift_x", st);
+  for (int i0 = 0; i0 < n; i0 += kMaxCubesPerLaunch) {
+    const int g = std::min(kMaxCubesPerLaunch, n - i0);
+    LinePass c = base_pass(ctx, P);
+    c.src_fs = c.dst_fs = (long long)N * N;
+    c.src_ls = c.dst_ls = 1;
+    c.src_ps = c.dst_ps = N;
+    c.line_lo = o;
+    c.n_lines = N;
+    c.in_off = o;
+    c.in_len = N;
+    c.out_off = o;
+    c.out_len = N;
+    c.dst_line_lo = o;
+    c.mirror = 0;
+    c.n_jobs = N / 2;
+    c.n_cubes = g;
+    long long F = 0;
+    for (int k = 0; k < g; ++k) {
+      c.cubes[k] = CubeRef{it[i0 + k].in, it[i0 + k].out, it[i0 + k].dy, F};
+      F += it[i0 + k].T;
+    }
+    c.n_frames = F;
+    graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
+    if (s != GRAPHIC_OK) return s;
+    LinePass r = c;
+    r.src_ls = r.dst_ls = N;
+    r.src_ps = r.dst_ps = 1;
+    for (int k = 0; k < g; ++k)
+      r.cubes[k] = CubeRef{it[i0 + k].out, it[i0 + k].out, it[i0 + k].dx, c.cubes[k].frame0};
+    if ((s = run_pass(ctx, r, kRowPass, "shift_x", st)) != GRAPHIC_OK) return s;
+  }
+  return GRAPHIC_OK;
 }
 
-// Rotation of frames [0, T) of `src` into `dst` (may alias src).
-graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float* src, float* dst, const double* theta, double sign, void* ws, size_t ws_bytes,
-                         hipStream_t st) {
-  RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, ws_bytes);
+// Three-shear rotation (Sect. 3.4) of every frame of the class, chunked over
+// the concatenated frames; a chunk may span cubes (at most
+// kMaxCubesPerLaunch of them).  dst may alias src.
+graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it, int n, double sign, void* ws,
+                               size_t ws_bytes, hipStream_t st) {
+  long long F = 0;
+  std::vector<long long> start(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    start[i] = F;
+    F += it[i].T;
+  }
+  start[n] = F;
+  RotLayout L = rot_layout(F, N, P, ctx->chunk_bytes, ws_bytes);
   if (L.chunk_frames < 1) return GRAPHIC_ERR_WORKSPACE;
   char* w = static_cast<char*>(ws);
   int* flip = reinterpret_cast<int*>(w);
-  double* ntan = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)));
-  double* sn = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)) + align_up((size_t)T * sizeof(double)));
-  int* flip_list = reinterpret_cast<int*>(w + align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double)));
-  int* flip_count = reinterpret_cast<int*>(reinterpret_cast<char*>(flip_list) + align_up((size_t)T * sizeof(int)));
+  double* ntan = reinterpret_cast<double*>(w + align_up((size_t)F * sizeof(int)));
+  double* sn = reinterpret_cast<double*>(w + align_up((size_t)F * sizeof(int)) + align_up((size_t)F * sizeof(double)));
+  int* flip_list = reinterpret_cast<int*>(w + align_up((size_t)F * sizeof(int)) + 2 * align_up((size_t)F * sizeof(double)));
+  int* flip_count = reinterpret_cast<int*>(reinterpret_cast<char*>(flip_list) + align_up((size_t)F * sizeof(int)));
   float* scratch = reinterpret_cast<float*>(w + L.params);
-  {
+  for (int i = 0; i < n; ++i) {
     Timer t(ctx, st, "aux");
-    hipError_t e = launch_rotation_params(theta, sign, T, flip, ntan, sn, st);
+    hipError_t e = launch_rotation_params(it[i].theta, sign, it[i].T, flip + start[i], ntan + start[i],
+                                          sn + start[i], st);
     t.done();
     if (e != hipSuccess) return GRAPHIC_ERR_HIP;
   }
   const int o = (P - N) / 2;
-  for (long long f0 = 0; f0 < T; f0 += (long long)L.chunk_frames) {
-    const long long nf = std::min<long long>((long long)L.chunk_frames, T - f0);
+  int c0 = 0;   // first cube of the current chunk
+  for (long long f0 = 0; f0 < F;) {
+    while (start[c0 + 1] <= f0) ++c0;
+    const int c1 = std::min(n, c0 + kMaxCubesPerLaunch);   // cubes [c0, c1) may take part
+    const long long nf = std::min<long long>((long long)L.chunk_frames, start[c1] - f0);
     {
       Timer t(ctx, st, "aux");
       hipError_t e = launch_flip_list(flip, f0, nf, flip_list, flip_count, st);
       t.done();
       if (e != hipSuccess) return GRAPHIC_ERR_HIP;
     }
-    // x-shear 1: window rows -> all P columns of the scratch frame
+    int ncub = 0;
+    while (c0 + ncub < c1 && start[c0 + ncub] < f0 + nf) ++ncub;
+    // x-shear 1: window rows of every cube frame -> all P columns of the scratch frame
     LinePass a = base_pass(ctx, P);
-    a.src = src + f0 * (long long)N * N;
     a.dst = scratch;
     a.src_fs = (long long)N * N;
     a.dst_fs = (long long)N * P;
@@ -303,6 +338,8 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     a.flip_src_reverse = 1;
     a.flip_lines = 1;
     a.flip_in_off = 1;
+    a.n_cubes = ncub;
+    for (int k = 0; k < ncub; ++k) a.cubes[k] = CubeRef{it[c0 + k].src, nullptr, nullptr, start[c0 + k] - f0};
     graphic_status s = run_pass(ctx, a, kRowPass, "shear_x1", st);
     if (s != GRAPHIC_OK) return s;
     // y-shear: every scratch column, window rows in and out (in place)
@@ -327,12 +364,10 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     b.flip_list = flip_list;
     b.flip_count = flip_count;
     b.flip_in_off = 1;
-    s = run_pass(ctx, b, kColPass, "shear_y", st);
-    if (s != GRAPHIC_OK) return s;
-    // x-shear 2: window rows, all P columns in, window columns out
+    if ((s = run_pass(ctx, b, kColPass, "shear_y", st)) != GRAPHIC_OK) return s;
+    // x-shear 2: window rows, all P columns in, window columns out to every cube frame
     LinePass c = base_pass(ctx, P);
     c.src = scratch;
-    c.dst = dst + f0 * (long long)N * N;
     c.src_fs = (long long)N * P;
     c.dst_fs = (long long)N * N;
     c.src_ls = P;
@@ -350,8 +385,10 @@ graphic_status do_rotate(graphic_ctx ctx, long long T, int N, int P, const float
     c.n_jobs = N / 2 + 1;
     c.n_frames = nf;
     c.sh1 = ntan + f0;
-    s = run_pass(ctx, c, kRowPass, "shear_x2", st);
-    if (s != GRAPHIC_OK) return s;
+    c.n_cubes = ncub;
+    for (int k = 0; k < ncub; ++k) c.cubes[k] = CubeRef{nullptr, it[c0 + k].dst, nullptr, start[c0 + k] - f0};
+    if ((s = run_pass(ctx, c, kRowPass, "shear_x2", st)) != GRAPHIC_OK) return s;
+    f0 += nf;
   }
   return GRAPHIC_OK;
 }
@@ -376,6 +413,113 @@ bool ws_ok(const void* ws, size_t have, size_t need) {
   if (need == 0) return true;
   if (!ws || have < need) return false;
   return (reinterpret_cast<uintptr_t>(ws) % kAlign) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// ADI reduction of a batch of cubes (Sect. 3.3 and 3.4)
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  std::vector<int> P;                   // working size of every cube
+  std::vector<std::vector<int>> classes;  // cube indices of every (N, P) class, in input order
+  std::vector<size_t> stack_off, psf_off; // workspace offsets (SIZE_MAX: caller-provided)
+  size_t fixed = 0;                     // bytes of stacks and PSFs
+  size_t rot_min = 0, rot_default = 0;  // rotation workspace: minimum and default
+};
+
+graphic_status plan_batch(const graphic_cube_desc* d, int n, uint32_t flags, size_t chunk_bytes, BatchPlan* plan) {
+  if (!d || n < 1) return GRAPHIC_ERR_ARG;
+  if ((flags & ~GRAPHIC_BATCH_INPLACE) != 0) return GRAPHIC_ERR_ARG;
+  plan->P.assign(n, 0);
+  plan->stack_off.assign(n, SIZE_MAX);
+  plan->psf_off.assign(n, SIZE_MAX);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    graphic_geom g{d[i].n_frames, d[i].n, d[i].pad, 0u};
+    graphic_status s = check_geom(&g, &plan->P[i]);
+    if (s != GRAPHIC_OK) return s;
+    if (d[i].n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+    if (!d[i].cube || !d[i].dx || !d[i].dy || !d[i].parang_deg || !d[i].final_img) return GRAPHIC_ERR_ARG;
+    const size_t cube_b = (size_t)d[i].n_frames * d[i].n * d[i].n * sizeof(float);
+    if (!d[i].residuals && !(flags & GRAPHIC_BATCH_INPLACE)) {
+      plan->stack_off[i] = off;
+      off += align_up(cube_b);
+    }
+    if (!d[i].psf) {
+      plan->psf_off[i] = off;
+      off += align_up((size_t)d[i].n * d[i].n * sizeof(float));
+    }
+    bool found = false;
+    for (auto& c : plan->classes)
+      if (d[c[0]].n == d[i].n && plan->P[c[0]] == plan->P[i]) {
+        c.push_back(i);
+        found = true;
+        break;
+      }
+    if (!found) plan->classes.push_back({i});
+  }
+  plan->fixed = off;
+  for (auto& c : plan->classes) {
+    long long F = 0;
+    for (int i : c) F += d[i].n_frames;
+    const int N = d[c[0]].n, P = plan->P[c[0]];
+    const RotLayout L = rot_layout(F, N, P, chunk_bytes, 0);
+    plan->rot_min = std::max(plan->rot_min, L.params + align_up((size_t)N * P * sizeof(float)));
+    plan->rot_default = std::max(plan->rot_default, L.total);
+  }
+  return GRAPHIC_OK;
+}
+
+graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uint32_t flags, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  BatchPlan plan;
+  graphic_status s = plan_batch(d, n, flags, ctx->chunk_bytes, &plan);
+  if (s != GRAPHIC_OK) return s;
+  // argument checks: outputs must not overlap the inputs of any cube
+  for (int i = 0; i < n; ++i) {
+    const size_t cube_b = (size_t)d[i].n_frames * d[i].n * d[i].n * sizeof(float);
+    const size_t img_b = (size_t)d[i].n * d[i].n * sizeof(float);
+    const char* cb = static_cast<const char*>(static_cast<const void*>(d[i].cube));
+    auto inside = [&](const void* p, size_t b) {
+      const char* q = static_cast<const char*>(p);
+      return q < cb + cube_b && cb < q + b;
+    };
+    if (inside(d[i].final_img, img_b)) return GRAPHIC_ERR_ARG;
+    if (d[i].psf && (inside(d[i].psf, img_b) || d[i].psf == d[i].final_img)) return GRAPHIC_ERR_ARG;
+    if (d[i].residuals && inside(d[i].residuals, cube_b)) return GRAPHIC_ERR_ARG;
+  }
+  if (!ws_ok(ws, ws_bytes, plan.fixed + plan.rot_min)) return GRAPHIC_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  char* w = static_cast<char*>(ws);
+  std::vector<float*> stack(n), psf(n);
+  for (int i = 0; i < n; ++i) {
+    stack[i] = d[i].residuals ? d[i].residuals
+               : (flags & GRAPHIC_BATCH_INPLACE) ? const_cast<float*>(d[i].cube)
+                                                 : reinterpret_cast<float*>(w + plan.stack_off[i]);
+    psf[i] = d[i].psf ? d[i].psf : reinterpret_cast<float*>(w + plan.psf_off[i]);
+  }
+  void* rot_ws = w + plan.fixed;
+  const size_t rot_bytes = ws_bytes - plan.fixed;
+  for (auto& c : plan.classes) {
+    const int N = d[c[0]].n, P = plan.P[c[0]];
+    std::vector<ShiftItem> sh;
+    std::vector<RotItem> rot;
+    for (int i : c) {
+      sh.push_back(ShiftItem{d[i].cube, stack[i], d[i].n_frames, d[i].dx, d[i].dy});
+      rot.push_back(RotItem{stack[i], stack[i], d[i].n_frames, d[i].parang_deg});
+    }
+    // S_i = shift(cube_i): every cube of the class in the same launches
+    if ((s = do_shift_batch(ctx, N, P, sh.data(), (int)sh.size(), st)) != GRAPHIC_OK) return s;
+    // PSF = median_i S_i; the median also rewrites the stack as S_i - PSF
+    for (int i : c)
+      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], psf[i], stack[i], st)) != GRAPHIC_OK) return s;
+    // D_i = rotate(S_i - PSF, -parang_i), in place
+    if ((s = do_rotate_batch(ctx, N, P, rot.data(), (int)rot.size(), -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
+      return s;
+    // final = median_i D_i
+    for (int i : c)
+      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], d[i].final_img, nullptr, st)) != GRAPHIC_OK) return s;
+  }
+  return GRAPHIC_OK;
 }
 
 }  // namespace
@@ -446,7 +590,19 @@ graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geo
   switch (op) {
     case GRAPHIC_OP_SHIFT: *bytes = shift_ws(T, N, P); return GRAPHIC_OK;
     case GRAPHIC_OP_ROTATE: *bytes = rot_layout(T, N, P, chunk, 0).total; return GRAPHIC_OK;
-    case GRAPHIC_OP_ADI: *bytes = adi_ws(T, N, P, chunk, false, false); return GRAPHIC_OK;
+    case GRAPHIC_OP_ADI: {
+      graphic_cube_desc d{};
+      d.cube = reinterpret_cast<const float*>(kAlign);   // placeholders: only the geometry matters here
+      d.n_frames = T;
+      d.n = N;
+      d.pad = geom->pad;
+      d.dx = d.dy = d.parang_deg = reinterpret_cast<const double*>(kAlign);
+      d.final_img = reinterpret_cast<float*>(kAlign);
+      BatchPlan plan;
+      if ((s = plan_batch(&d, 1, 0u, chunk, &plan)) != GRAPHIC_OK) return s;
+      *bytes = plan.fixed + plan.rot_default;
+      return GRAPHIC_OK;
+    }
     case GRAPHIC_OP_MEDIAN: *bytes = 0; return T > kMaxT_Median ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
     default: return GRAPHIC_ERR_ARG;
   }
@@ -468,7 +624,8 @@ graphic_status graphic_shift(graphic_ctx ctx, const graphic_geom* geom, const fl
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
   if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
-  if ((s = do_shift(ctx, T, N, P, in, out, dx, dy, st)) != GRAPHIC_OK) return s;
+  const ShiftItem item{in, out, T, dx, dy};
+  if ((s = do_shift_batch(ctx, N, P, &item, 1, st)) != GRAPHIC_OK) return s;
   if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
 }
@@ -491,7 +648,8 @@ graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom, const f
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
   if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
-  if ((s = do_rotate(ctx, T, N, P, in, out, theta_deg, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
+  const RotItem item{in, out, T, theta_deg};
+  if ((s = do_rotate_batch(ctx, N, P, &item, 1, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
   if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
 }
@@ -515,42 +673,36 @@ graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const f
 graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, const float* cube, const double* dx,
                                   const double* dy, const double* parang_deg, float* final_img, float* psf,
                                   float* residuals, void* ws, size_t ws_bytes, graphic_stream stream) {
-  int P = 0;
-  if (!ctx) return GRAPHIC_ERR_ARG;
-  graphic_status s = check_geom(geom, &P);
+  if (!ctx || !geom) return GRAPHIC_ERR_ARG;
+  if (geom->flags != 0) return GRAPHIC_ERR_ARG;
+  graphic_cube_desc d;
+  d.cube = cube;
+  d.n_frames = geom->n_frames;
+  d.n = geom->n;
+  d.pad = geom->pad;
+  d.dx = dx;
+  d.dy = dy;
+  d.parang_deg = parang_deg;
+  d.final_img = final_img;
+  d.psf = psf;
+  d.residuals = residuals;
+  return adi_batch(ctx, &d, 1, 0u, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                            uint32_t flags, size_t* bytes) {
+  if (!bytes) return GRAPHIC_ERR_ARG;
+  BatchPlan plan;
+  graphic_status s = plan_batch(descs, n_cubes, flags, ctx ? ctx->chunk_bytes : kDefaultChunkBytes, &plan);
   if (s != GRAPHIC_OK) return s;
-  if (!cube || !dx || !dy || !parang_deg || !final_img) return GRAPHIC_ERR_ARG;
-  const long long T = geom->n_frames;
-  const int N = geom->n;
-  if (T > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
-  const size_t cube_bytes = (size_t)T * N * N * sizeof(float);
-  const size_t img_bytes = (size_t)N * N * sizeof(float);
-  if (residuals && overlap_bad(cube, residuals, cube_bytes)) return GRAPHIC_ERR_ARG;
-  if (residuals && residuals == cube) return GRAPHIC_ERR_ARG;
-  if (overlap_bad(cube, final_img, img_bytes) ||
-      ((const char*)final_img >= (const char*)cube && (const char*)final_img < (const char*)cube + cube_bytes))
-    return GRAPHIC_ERR_ARG;
-  if (psf && psf == final_img) return GRAPHIC_ERR_ARG;
-  // workspace: [stack of shifted frames unless residuals given][psf unless given][rotation]
-  const size_t stack_b = residuals ? 0 : align_up(cube_bytes);
-  const size_t psf_b = psf ? 0 : align_up(img_bytes);
-  const RotLayout L0 = rot_layout(T, N, P, ctx->chunk_bytes, 0);
-  const size_t minimum = stack_b + psf_b + L0.params + align_up((size_t)N * P * sizeof(float));
-  if (!ws_ok(ws, ws_bytes, minimum)) return GRAPHIC_ERR_WORKSPACE;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
-  char* w = static_cast<char*>(ws);
-  float* stack = residuals ? residuals : reinterpret_cast<float*>(w);
-  float* psf_buf = psf ? psf : reinterpret_cast<float*>(w + stack_b);
-  void* rot_ws = w + stack_b + psf_b;
-  const size_t rot_bytes = ws_bytes - stack_b - psf_b;
-  if ((s = do_shift(ctx, T, N, P, cube, stack, dx, dy, st)) != GRAPHIC_OK) return s;
-  // the PSF median also rewrites the stack as residuals S_i - PSF (Sect. 3.3),
-  // so the rotation reads them directly
-  if ((s = do_median(ctx, T, N, stack, psf_buf, stack, st)) != GRAPHIC_OK) return s;
-  if ((s = do_rotate(ctx, T, N, P, stack, stack, parang_deg, -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
-    return s;
-  return do_median(ctx, T, N, stack, final_img, nullptr, st);
+  *bytes = plan.fixed + plan.rot_default;
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_adi_reduce_batch(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                        uint32_t flags, void* ws, size_t ws_bytes, graphic_stream stream) {
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  return adi_batch(ctx, descs, n_cubes, flags, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 graphic_status graphic_timing_enable(graphic_ctx ctx, int enable) {

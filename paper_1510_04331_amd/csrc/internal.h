@@ -20,6 +20,18 @@ struct TwiddleTables {
   const float2* fold;
 };
 
+constexpr int kMaxCubesPerLaunch = 16;
+
+// One cube of a batched launch: frames [frame0, frame0 + n) of the launch
+// belong to it (frame0 may be negative when the launch starts inside it).
+// A null member means "the launch's own array, indexed by the launch frame".
+struct CubeRef {
+  const float* src;       // the cube's frame 0 in the pass's source, or null
+  float* dst;             // the cube's frame 0 in the pass's destination, or null
+  const double* sh0;      // the cube's per-frame constant shift (local frame index), or null
+  long long frame0;
+};
+
 // One pass of one-dimensional Fourier shifts over the lines of a stack of
 // 2-D arrays.  Coordinates along and across the lines are those of the
 // zero-padded P x P frame; the mapping to array indices is described by the
@@ -42,6 +54,12 @@ struct LinePass {
   int n_jobs;             // jobs (line pairs) per frame
   long long n_frames;
   int blocks_per_frame;   // set by the launcher: blocks never straddle frames
+
+  // Batched launches: with n_cubes > 0, frame f of the launch lives in the
+  // cube with the largest frame0 <= f, and src/dst/sh0 come from that cube
+  // (sh1 and flip stay indexed by the launch's frame f).
+  int n_cubes;
+  CubeRef cubes[kMaxCubesPerLaunch];
 
   // shift of line l in frame f: sh0[f] + sh1[f] * (l - P/2)   (either may be null)
   const double* sh0;

@@ -209,8 +209,23 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int rb = (lb2 - line_lo + P) & (P - 1);
   const bool a_ok = job_ok && ra < p.n_lines;
   const bool b_ok = job_ok && b_exists && rb < p.n_lines;
+  // frame -> source / destination arrays (and constant shift) of its cube
+  // (a null array in the cube entry means the launch's own array, indexed by f)
+  const float* src_base = p.src;
+  float* dst_base = p.dst;
+  const double* sh0 = p.sh0;
+  long long fsrc = f, fdst = f, fsh = f;
+  if (p.n_cubes > 0) {
+    int ci = 0;
+    for (int q2 = 1; q2 < p.n_cubes; ++q2)
+      if ((long long)f >= p.cubes[q2].frame0) ci = q2;
+    const long long fl = (long long)f - p.cubes[ci].frame0;
+    if (p.cubes[ci].src) { src_base = p.cubes[ci].src; fsrc = fl; }
+    if (p.cubes[ci].dst) { dst_base = p.cubes[ci].dst; fdst = fl; }
+    if (p.cubes[ci].sh0) { sh0 = p.cubes[ci].sh0; fsh = fl; }
+  }
   double s = 0.0;
-  if (p.sh0) s += p.sh0[f];
+  if (sh0) s += sh0[fsh];
   if (p.sh1) s += p.sh1[f] * (double)(la - c);
   const double q = s / (double)P;
 
@@ -222,8 +237,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int lia = rev ? (p.n_lines - 1 - ra) : ra;
   const int lib = rev ? (p.n_lines - 1 - rb) : rb;
 
-  const __amdgpu_buffer_rsrc_t src = make_rsrc(p.src + (size_t)f * p.src_fs, (unsigned)p.src_fs * 4u);
-  const __amdgpu_buffer_rsrc_t dst = make_rsrc(p.dst + (size_t)f * p.dst_fs, (unsigned)p.dst_fs * 4u);
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(src_base + (size_t)fsrc * p.src_fs, (unsigned)p.src_fs * 4u);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc(dst_base + (size_t)fdst * p.dst_fs, (unsigned)p.dst_fs * 4u);
   const __amdgpu_buffer_rsrc_t tfold = make_rsrc(p.tw.fold, 2u * M * 8u);
   const __amdgpu_buffer_rsrc_t tfwd = make_rsrc(p.tw.fwd, (unsigned)M * 8u);
   const __amdgpu_buffer_rsrc_t tinv = make_rsrc(p.tw.inv, (unsigned)M * 8u);

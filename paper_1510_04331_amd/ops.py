@@ -32,6 +32,19 @@ def _stream(dev):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
+def _on_stream(stream, dev, tensors):
+    """Stream handle for a call; a side stream first waits for the current
+    stream (which produced the arguments) and keeps the tensors alive."""
+    import torch
+    if stream is None:
+        return _stream(dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
 def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
@@ -116,7 +129,7 @@ def median(stack, out=None):
     return out
 
 
-def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, workspace=None):
+def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, workspace=None, stream=None):
     """Classical ADI: recentre, median PSF, subtract, derotate by -parang,
     median combine.  Returns the final image, plus the PSF and the derotated
     residual cube when asked."""
@@ -134,14 +147,84 @@ def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, w
         ws, n = workspace, workspace.numel()
     g = _geom(T, N, pad)
     lib = _abi.load()
+    st = _on_stream(stream, dev, [cube, dx, dy, pa, final, psf_t, res_t, ws])
     _abi.check(lib.graphic_adi_reduce(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(dx), _ptr(dy),
-                                      _ptr(pa), _ptr(final), _ptr(psf_t), _ptr(res_t), _ptr(ws), n,
-                                      _stream(dev)), "graphic_adi_reduce")
+                                      _ptr(pa), _ptr(final), _ptr(psf_t), _ptr(res_t), _ptr(ws), n, st),
+               "graphic_adi_reduce")
     out = [final]
     if psf:
         out.append(psf_t)
     if residuals:
         out.append(res_t)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def _batch_descs(cubes, dx, dy, parang, pad, psf, residuals):
+    import torch
+    n = len(cubes)
+    if not (len(dx) == len(dy) == len(parang) == n) or n < 1:
+        raise ValueError("one dx, dy and parang array per cube")
+    keep = []                      # tensors that must outlive the call
+    descs = (_abi.CubeDesc * n)()
+    finals, psfs, resids = [], [], []
+    dev = cubes[0].device
+    for i, c in enumerate(cubes):
+        T, N = _check_cube(c, "cubes[%d]" % i)
+        if c.device != dev:
+            raise ValueError("all cubes must be on one device")
+        a, b, p = _f64(dx[i], T, dev, "dx"), _f64(dy[i], T, dev, "dy"), _f64(parang[i], T, dev, "parang")
+        f = torch.empty((N, N), dtype=torch.float32, device=dev)
+        ps = torch.empty((N, N), dtype=torch.float32, device=dev) if psf else None
+        rs = torch.empty_like(c) if residuals else None
+        keep += [a, b, p]
+        finals.append(f)
+        psfs.append(ps)
+        resids.append(rs)
+        descs[i] = _abi.CubeDesc(c.data_ptr(), T, N, int(pad or 0), a.data_ptr(), b.data_ptr(), p.data_ptr(),
+                                 f.data_ptr(), 0 if ps is None else ps.data_ptr(),
+                                 0 if rs is None else rs.data_ptr())
+    return descs, keep, finals, psfs, resids
+
+
+def batch_workspace_size(cubes, pad=None, inplace=False, device_index=0):
+    """Workspace bytes of adi_reduce_batch for these cubes (shapes only)."""
+    import torch
+    n = len(cubes)
+    descs = (_abi.CubeDesc * n)()
+    for i, c in enumerate(cubes):
+        T, N = c.shape[0], c.shape[1]
+        descs[i] = _abi.CubeDesc(256, T, N, int(pad or 0), 256, 256, 256, 256, 0, 0)
+    out = ctypes.c_size_t()
+    flags = _abi.BATCH_INPLACE if inplace else 0
+    _abi.check(_abi.load().graphic_batch_workspace_size(context(device_index), descs, n, flags,
+                                                        ctypes.byref(out)), "graphic_batch_workspace_size")
+    return out.value
+
+
+def adi_reduce_batch(cubes, dx, dy, parang_deg, pad=None, inplace=False, psf=False, residuals=False,
+                     workspace=None, stream=None):
+    """ADI reduction of several cubes (uneven frame counts and sizes) in
+    batched launches.  Returns the list of final images (and PSFs /
+    residual cubes when asked).  With ``inplace`` every input cube is
+    overwritten with its derotated residuals."""
+    import torch
+    dev = cubes[0].device
+    descs, keep, finals, psfs, resids = _batch_descs(cubes, dx, dy, parang_deg, pad, psf, residuals)
+    flags = _abi.BATCH_INPLACE if inplace else 0
+    if workspace is None:
+        n = ctypes.c_size_t()
+        _abi.check(_abi.load().graphic_batch_workspace_size(context(dev.index or 0), descs, len(cubes), flags,
+                                                            ctypes.byref(n)), "graphic_batch_workspace_size")
+        workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+    st = _on_stream(stream, dev, list(cubes) + keep + finals + psfs + resids + [workspace])
+    _abi.check(_abi.load().graphic_adi_reduce_batch(context(dev.index or 0), descs, len(cubes), flags,
+                                                    _ptr(workspace), workspace.numel(), st),
+               "graphic_adi_reduce_batch")
+    out = [finals]
+    if psf:
+        out.append(psfs)
+    if residuals:
+        out.append(resids)
     return out[0] if len(out) == 1 else tuple(out)
 
 
