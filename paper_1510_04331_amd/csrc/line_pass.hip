@@ -86,12 +86,46 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
   return {re * scale, im * scale};
 }
 
-// Occupancy target (waves per SIMD) that bounds the register budget.
-#ifndef GRAPHIC_COL_WAVES_1024
-#define GRAPHIC_COL_WAVES_1024 2
+// Launch shape of the column passes per half-size M: jobs per block (G),
+// occupancy target in waves per SIMD (W, which bounds the register budget)
+// and whether the exchanges use separate real / imaginary buffers (DB: fewer
+// barriers, twice the LDS).  Measured on MI355X; each can be overridden at
+// build time.
+#ifndef GRAPHIC_COL_G_256
+#define GRAPHIC_COL_G_256 16
 #endif
-#ifndef GRAPHIC_COL_JOBS_1024
-#define GRAPHIC_COL_JOBS_1024 8
+#ifndef GRAPHIC_COL_W_256
+#define GRAPHIC_COL_W_256 4
+#endif
+#ifndef GRAPHIC_COL_DB_256
+#define GRAPHIC_COL_DB_256 1
+#endif
+#ifndef GRAPHIC_COL_G_512
+#define GRAPHIC_COL_G_512 8
+#endif
+#ifndef GRAPHIC_COL_W_512
+#define GRAPHIC_COL_W_512 2
+#endif
+#ifndef GRAPHIC_COL_DB_512
+#define GRAPHIC_COL_DB_512 1
+#endif
+#ifndef GRAPHIC_COL_G_1024
+#define GRAPHIC_COL_G_1024 8
+#endif
+#ifndef GRAPHIC_COL_W_1024
+#define GRAPHIC_COL_W_1024 4
+#endif
+#ifndef GRAPHIC_COL_DB_1024
+#define GRAPHIC_COL_DB_1024 0
+#endif
+#ifndef GRAPHIC_COL_G_2048
+#define GRAPHIC_COL_G_2048 8
+#endif
+#ifndef GRAPHIC_COL_W_2048
+#define GRAPHIC_COL_W_2048 2
+#endif
+#ifndef GRAPHIC_COL_DB_2048
+#define GRAPHIC_COL_DB_2048 0
 #endif
 #ifndef GRAPHIC_COL_WAVE_LAYOUT
 #define GRAPHIC_COL_WAVE_LAYOUT 0
@@ -108,9 +142,22 @@ constexpr bool lanes_on_jobs() {
   return KIND == kColPass && !GRAPHIC_COL_WAVE_LAYOUT;
 }
 
+template <int M>
+constexpr bool col_db() {
+  return lanes_on_jobs<kColPass>() &&
+         (M == 256 ? GRAPHIC_COL_DB_256 : M == 512 ? GRAPHIC_COL_DB_512 : M == 1024 ? GRAPHIC_COL_DB_1024
+          : M == 2048 ? GRAPHIC_COL_DB_2048 : 1);
+}
+
 template <int M, int KIND>
 constexpr int waves_per_eu() {
-  return M <= 256 ? 4 : (M == 1024 ? (lanes_on_jobs<KIND>() ? GRAPHIC_COL_WAVES_1024 : 3) : 2);
+  if (KIND == kColPass && lanes_on_jobs<KIND>()) {
+    if (M == 256) return GRAPHIC_COL_W_256;
+    if (M == 512) return GRAPHIC_COL_W_512;
+    if (M == 1024) return GRAPHIC_COL_W_1024;
+    if (M == 2048) return GRAPHIC_COL_W_2048;
+  }
+  return M <= 256 ? 4 : (M == 1024 ? 3 : 2);
 }
 
 typedef int v2i __attribute__((ext_vector_type(2)));
@@ -141,7 +188,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // for real and imaginary parts, so each exchange needs one barrier.  Row
   // blocks are one wave (barriers are free, LDS bounds occupancy): one buffer.
   constexpr bool LJ = lanes_on_jobs<KIND>();
-  constexpr bool DB = LJ;
+  constexpr bool DB = LJ && col_db<M>();
   constexpr int BUF = G * 2 * S::HALF;
   extern __shared__ float lds_raw[];
   float* lds = lds_raw;
@@ -500,8 +547,11 @@ line_pass_flipped_kernel(const LinePass p) {
 template <int M>
 constexpr int col_jobs_per_block() {
   using S = Shape<M>;
-  if (M == 1024) return GRAPHIC_COL_JOBS_1024;
   if (!lanes_on_jobs<kColPass>()) return 64 / S::JOB > 0 ? 64 / S::JOB : 1;
+  if (M == 256) return GRAPHIC_COL_G_256;
+  if (M == 512) return GRAPHIC_COL_G_512;
+  if (M == 1024) return GRAPHIC_COL_G_1024;
+  if (M == 2048) return GRAPHIC_COL_G_2048;
   constexpr int budget = 140 * 1024;
   int g = 16;
   while (g > 1 && (g * S::PER_JOB_F_DB * 4 > budget || g * S::JOB > 1024)) g /= 2;
@@ -516,10 +566,14 @@ constexpr int row_jobs_per_block() {
 template <int M, int KIND, int G, int IO, bool MIR>
 static hipError_t launch_g(LinePass p, hipStream_t st) {
   using S = Shape<M>;
+  static_assert(G * S::JOB <= 1024, "block too large");
+  static_assert(G * (lanes_on_jobs<KIND>() && col_db<M>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * 4 <= 160 * 1024,
+                "LDS per block above 160 KiB");
   p.blocks_per_frame = (p.n_jobs + G - 1) / G;
   const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds = (size_t)G * (lanes_on_jobs<KIND>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * sizeof(float);
+  const size_t lds =
+      (size_t)G * (lanes_on_jobs<KIND>() && col_db<M>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * sizeof(float);
   hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
