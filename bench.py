@@ -7,6 +7,15 @@ SPHERE-like cube of 4096 frames of 1024 x 1024 float32 (zero-padded to
 2048 x 2048), with the cube already resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Two more workloads print their own JSON line:
+
+    python bench.py --workload batch    64 uneven cubes (T log-uniform in
+        [32, 2048], N in {256, 512, 1024, 2048}) reduced in place by one
+        batched call, against one call per cube
+    python bench.py --workload served   Poisson arrivals (20 requests/s) of
+        such cubes through the request loop (HBM-budget admission, four
+        streams), against one request at a time
 """
 
 import argparse
@@ -71,6 +80,131 @@ def cpu_baseline(frames_per_core=2):
                       % (len(idx), dt)}
 
 
+# ---------------------------------------------------------------------------
+# Batched and served workloads.  Each cube's frames are copies of a pool of
+# rendered frames of its size (64 per size, generated once on the device), so
+# that filling a cube costs one device copy; the per-frame shifts and angles
+# are the cube's own.
+# ---------------------------------------------------------------------------
+POOL_FRAMES = 64
+
+
+def _pools(torch, dev, sizes):
+    import synth
+    pools = {}
+    for k, N in enumerate(sorted(set(sizes))):
+        p = synth.make_params(2, seed=synth.BASE_SEED + 100 + k, T=POOL_FRAMES, N=N)
+        pools[N] = synth.render_device(p, dev)
+    torch.cuda.synchronize()
+    return pools
+
+
+def _fill(pools, N):
+    src = pools[N]
+
+    def fill(cube, stream=None):
+        T = cube.shape[0]
+        for s0 in range(0, T, POOL_FRAMES):
+            n = min(POOL_FRAMES, T - s0)
+            cube[s0:s0 + n].copy_(src[:n])
+    return fill
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+    import paper_1510_04331_amd as G
+    import synth
+    dev = torch.device("cuda:0")
+    ps = synth.make_batch_params(64, with_screen=False)
+    pools = _pools(torch, dev, [p.N for p in ps])
+    cubes = [torch.empty((p.T, p.N, p.N), dtype=torch.float32, device=dev) for p in ps]
+    fills = [_fill(pools, p.N) for p in ps]
+    dx = [torch.tensor(p.dx, dtype=torch.float64, device=dev) for p in ps]
+    dy = [torch.tensor(p.dy, dtype=torch.float64, device=dev) for p in ps]
+    pa = [torch.tensor(p.parang, dtype=torch.float64, device=dev) for p in ps]
+    ws = torch.empty(G.batch_workspace_size(cubes, inplace=True), dtype=torch.uint8, device=dev)
+    frames = sum(p.T for p in ps)
+    print("batch: %d cubes, %d frames, %.1f GiB" % (len(ps), frames, sum(c.numel() for c in cubes) * 4 / 2**30),
+          file=sys.stderr, flush=True)
+
+    def refill():
+        for c, f in zip(cubes, fills):
+            f(c)
+        torch.cuda.synchronize()
+
+    def timed(fn, steps):
+        ts = []
+        for _ in range(steps):
+            refill()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return ts
+
+    def batched():
+        G.adi_reduce_batch(cubes, dx, dy, pa, inplace=True, workspace=ws)
+
+    def per_cube():
+        for i in range(len(cubes)):
+            G.adi_reduce_batch([cubes[i]], [dx[i]], [dy[i]], [pa[i]], inplace=True, workspace=ws)
+
+    timed(batched, args.warmup)
+    tb = timed(batched, args.steps)
+    print("batched done", file=sys.stderr, flush=True)
+    timed(per_cube, 1)
+    tp = timed(per_cube, args.steps)
+    mb, mp = min(tb), min(tp)
+    out = {"metric": "frames reduced/s, 64 uneven cubes in one batched call (vs one call per cube)",
+           "value": round(frames / mb, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * mb, 3), "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 cubes, T log-uniform in [32, 2048], N in {256,512,1024,2048}, P = 2N, "
+                                  "in-place full ADI reduction", "frames": frames,
+                      "bytes": int(sum(c.numel() for c in cubes) * 4)},
+           "per_cube_path": {"value": round(frames / mp, 1), "ms_per_step": round(1e3 * mp, 3)},
+           "step_ms_all": [round(1e3 * t, 3) for t in tb]}
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    import numpy as np
+    import torch
+    import synth
+    from paper_1510_04331_amd import serve
+    dev = torch.device("cuda:0")
+    n = args.requests
+    arr = synth.make_arrivals(n, rate=args.rate)
+    ps = synth.make_batch_params(n, seed=synth.BASE_SEED + 5, with_screen=False)
+    pools = _pools(torch, dev, [p.N for p in ps])
+    free_b, total_b = torch.cuda.mem_get_info(dev)
+    budget = int(args.budget_gib * 2**30) if args.budget_gib else int(0.6 * free_b)
+
+    def requests():
+        return [serve.Request(rid=i, arrival=float(arr[i]), T=p.T, N=p.N, dx=p.dx, dy=p.dy, parang=p.parang,
+                              fill=_fill(pools, p.N)) for i, p in enumerate(ps)]
+
+    res = {}
+    for name, slots, mb in (("served", args.slots, args.max_batch), ("one_at_a_time", 1, 1)):
+        ex = serve.TorchExecutor(dev, slots)
+        adm = serve.Admission(budget, slots, mb, ex.group_bytes, cost=ex.cost, big_cost=args.big_ms)
+        st = serve.run(requests(), ex, adm)
+        torch.cuda.synchronize()
+        res[name] = st.summary()
+        print("%s: %s" % (name, json.dumps(res[name])), file=sys.stderr, flush=True)
+    s = res["served"]
+    out = {"metric": "frames/s served at %.0f requests/s; p50/p99 request latency" % args.rate,
+           "value": s["frames_per_s"], "unit": "frames/s", "n_gpus": 1, "steps": n, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Poisson arrivals, %d requests at %.1f/s, cubes as in the 64-cube batch "
+                                  "(T log-uniform in [32, 2048], N in {256..2048})" % (n, args.rate),
+                      "slots": args.slots, "max_batch": args.max_batch, "hbm_budget_bytes": budget,
+                      "large_request_ms": args.big_ms},
+           "latency_ms": s["latency_ms"], "served": s, "one_at_a_time": res["one_at_a_time"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +213,14 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("adi", "batch", "served"), default="adi")
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--budget-gib", type=float, default=None)
+    ap.add_argument("--big-ms", type=float, default=50.0,
+                    help="estimated device time from which a served request runs alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the cube (known bytes) before the timed steps, "
                          "to scale hardware byte counters")
@@ -89,6 +231,10 @@ def main():
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is described in "
               "DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     cpu = None
     if not args.no_cpu_baseline:
