@@ -27,6 +27,38 @@ import time
 
 METRIC = "frames shifted+rotated/s at 1024² FP32 (% HBM roofline); cube p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sources_sha256():
+    """Hash of the library sources; a traffic record taken from other sources
+    no longer describes the kernels that run."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_1510_04331_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(path, fam, N, P):
+    """Measured HBM bytes per frame of one kernel family (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, calibrated), or None when absent or taken from other sources."""
+    try:
+        with open(path) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    sha = [ln.split()[1] for ln in lines if ln.startswith("source_sha256 ")]
+    if not sha or sha[0] != sources_sha256():
+        return None
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == fam and f[2] == "N=%d" % N and f[3] == "P=%d" % P:
+            return float(f[4].split("=")[1])
+    return None
 
 # Algorithmic HBM bytes per frame of each kernel family (float32, N x N frames,
 # working size P): one read of every stored input value and one write of every
@@ -224,8 +256,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the cube (known bytes) before the timed steps, "
                          "to scale hardware byte counters")
-    ap.add_argument("--traffic", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                       "profiles", "traffic.json"))
+    ap.add_argument("--traffic", default=os.path.join(HERE, "profiles", "traffic_adi_1024.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is described in "
@@ -305,14 +336,9 @@ def main():
         d["achieved_GBps"] = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
     dom = max((f for f in fams if "achieved_GBps" in fams[f]), key=lambda f: fams[f]["ms_per_step"])
     traffic = None
-    try:
-        with open(args.traffic) as fh:
-            tr = json.load(fh)
-        ent = tr.get(dom)
-        if ent and ent.get("N") == N and ent.get("frames_per_launch") == T / fams[dom]["launches_per_step"]:
-            traffic = ent["bytes_per_launch"]
-    except (OSError, ValueError):
-        pass
+    per_frame = read_traffic(args.traffic, dom, N, P)
+    if per_frame is not None:
+        traffic = round(per_frame * T / fams[dom]["launches_per_step"])
     sl = sorted(step_ms)
 
     def pct(q):
