@@ -12,9 +12,13 @@
 // 64 contiguous bytes of one frame).  Thread (pixel, g) keeps the keys of
 // frames g, g+64, g+128, ... in registers, so the stack is read from HBM once.
 // The rank-(T-1)/2 key is found by a most-significant-digit-first radix select
-// with four 8-bit digits; each digit builds a 256-bin histogram per pixel in
-// LDS and one wave per pixel scans it.  hi is lo itself when at least T/2+1
-// keys are <= lo, otherwise the smallest key above lo.
+// with up to four 8-bit digits; each digit builds a 256-bin histogram per
+// pixel in LDS and one wave per pixel scans it.  Every lane of a wave owns a
+// private sub-histogram (pixel, lane group) with two 16-bit counters per word,
+// so the atomic adds of one wave never collide on an address.  The select
+// stops early once every pixel's selected bin holds a single key.  hi is lo
+// itself when at least T/2+1 keys are <= lo, otherwise the smallest key above
+// lo.
 
 #include "internal.h"
 
@@ -28,7 +32,7 @@ namespace {
 
 constexpr int kGroups = 64;       // frame groups (threads) per pixel
 constexpr int kBins = 256;
-constexpr int kHistPitch = kBins + 1;   // +1 word: pixels land on distinct banks
+constexpr int kHistWords = kBins / 2 + 1;   // two 16-bit counters per word, +1: distinct banks
 
 __device__ __forceinline__ unsigned key_of(float v) {
   unsigned b = __float_as_uint(v);
@@ -63,39 +67,56 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
                                                                 long long npix, float* __restrict__ out,
                                                                 float* resid) {
   constexpr int kThreads = kPix * kGroups;
-  __shared__ unsigned hist[kPix * kHistPitch];
-  __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix];
+  constexpr int kSub = 64 / kPix;                  // lane groups of one pixel inside a wave
+  // one sub-histogram per (pixel, lane group); a counter sees at most
+  // (waves) x VPT = 1024 keys, so 16 bits suffice
+  static_assert((kThreads / 64) * VPT < 65536, "16-bit histogram counters");
+  __shared__ unsigned hist[kPix * kSub * kHistWords];
+  __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix], sel_lo[kPix];
   __shared__ float sel_med[kPix];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int px = lane % kPix;
-  const int g = lane / kPix + (64 / kPix) * wave;   // frame group 0..63
-  const long long pix = (long long)blockIdx.x * kPix + px;
+  const int sub = lane / kPix;
+  const int g = sub + kSub * wave;                 // frame group 0..63
+  // The hardware deals consecutive block ids to the eight XCDs in turn; the
+  // remap gives each XCD a contiguous run of pixel tiles, so the two 64-byte
+  // halves of a 128-byte line are read by blocks that run side by side on
+  // one L2 (and each frame row is read in long runs).
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const long long pix = (long long)tile * kPix + px;
   const bool pix_ok = pix < npix;
+  unsigned* my_hist = hist + (px * kSub + sub) * kHistWords;
 
-  // Frames 64 i .. 64 i + 63 form group i; one wave-uniform buffer descriptor
-  // per group keeps the per-lane address a single 32-bit offset
-  // (g * npix + pix) * 4, and offsets past the group's frames read 0.
-  const long long pix0 = (long long)blockIdx.x * kPix;
+  // Frames 64 i .. 64 i + 63 form group i.  One wave-uniform buffer
+  // descriptor per group keeps the per-lane address a single 32-bit offset
+  // (g * npix + px) * 4: the base advances by 64 frames per group, full groups
+  // share one extent, and the last group's extent ends after frame T - 1, so
+  // lanes past it (and groups past T) read 0 and their stores are dropped.
+  const int Ti = (int)T;                                   // T <= 4096
+  const long long pix0 = (long long)tile * kPix;
   const unsigned voff = pix_ok ? (unsigned)(((long long)g * npix + (pix - pix0)) * 4) : 0x80000000u;
-  auto group = [&](int i) {
-    const long long f0 = (long long)kGroups * i;
-    const long long nf = T - f0 < kGroups ? T - f0 : kGroups;
-    const long long bytes = nf > 0 ? (nf - 1) * npix * 4 + (npix - pix0) * 4 : 0;
-    return frames_rsrc(stack + f0 * npix + pix0, (unsigned)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL));
-  };
+  const unsigned extent = (unsigned)(((long long)(kGroups - 1) * npix + kPix) * 4);
+  const int last = (Ti - 1) / kGroups;
+  const unsigned extent_last =
+      (unsigned)((((long long)(Ti - 1) - (long long)kGroups * last) * npix + (npix - pix0)) * 4);
+  const unsigned long long gstride = (unsigned long long)kGroups * (unsigned long long)npix * 4ull;
+  auto group_ext = [&](int i) { return i < last ? extent : (i == last ? extent_last : 0u); };
   unsigned key[VPT];
+  unsigned long long gaddr = reinterpret_cast<unsigned long long>(stack + pix0);   // group i's base, advanced per group
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
-    const long long t = g + (long long)kGroups * i;
-    const bool valid = t < T;
+    const bool valid = g + kGroups * i < Ti;
     float v;
     if constexpr (BUF) {
-      v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(group(i), (int)voff, 0, 0));
+      v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          frames_rsrc(reinterpret_cast<const float*>(gaddr), group_ext(i)), (int)voff, 0, 0));
+      gaddr += gstride;
     } else {
-      v = (valid && pix_ok) ? stack[t * npix + pix] : 0.0f;   // frames too large for 32-bit offsets
+      v = (valid && pix_ok) ? stack[(long long)(g + kGroups * i) * npix + pix] : 0.0f;   // frames too large for 32-bit offsets
     }
     key[i] = valid ? key_of(v) : 0xFFFFFFFFu;   // padding sorts after every real (non-NaN) value
   }
@@ -104,30 +125,39 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   if (tid < kPix) {
     sel_prefix[tid] = 0u;
     sel_rank[tid] = k_lo;
+    sel_lo[tid] = 0xFFFFFFFFu;
   }
 
-  unsigned prefix = 0u, mask = 0u;
+  unsigned mask = 0u;
+  bool single = false;                              // every pixel's bin holds one key
 #pragma unroll 1
   for (int d = 3; d >= 0; --d) {
-    for (int i = tid; i < kPix * kHistPitch; i += kThreads) hist[i] = 0u;
+    for (int i = tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
     __syncthreads();
-    prefix = sel_prefix[px];
+    const unsigned prefix = sel_prefix[px];
     const int sh = 8 * d;
+    // (mask = 0 and prefix = 0 for the first digit: every key counts)
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      if ((key[i] & mask) == prefix) atomicAdd(&hist[px * kHistPitch + ((key[i] >> sh) & 0xFFu)], 1u);
+      if ((key[i] & mask) == prefix) {
+        const unsigned bin = (key[i] >> sh) & 0xFFu;
+        atomicAdd(&my_hist[bin >> 1], 1u << ((bin & 1u) << 4));
+      }
     }
     __syncthreads();
     // wave w scans the histogram of pixel w: lane l holds bins l, l+64, l+128, l+192
-    {
-      const int w = wave;
+    for (int w = wave; w < kPix; w += kThreads / 64) {
       const unsigned k = sel_rank[w];
       unsigned carry = 0u;
       int found_bin = -1;
       unsigned below = 0u, inbin = 0u;
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk) {
-        const unsigned x = hist[w * kHistPitch + blk * 64 + lane];
+        const int bin = blk * 64 + lane;
+        unsigned x = 0u;
+#pragma unroll
+        for (int q = 0; q < kSub; ++q) x += hist[(w * kSub + q) * kHistWords + (bin >> 1)];
+        x = (bin & 1) ? (x >> 16) : (x & 0xFFFFu);
         const unsigned incl = wave_incl_scan(x);
         const unsigned tot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
         const unsigned long long hit = __ballot(carry + incl > k);
@@ -150,12 +180,34 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
     }
     mask |= 0xFFu << sh;
     __syncthreads();
+    if (d > 0) {
+      unsigned most = 0u;
+#pragma unroll
+      for (int q = 0; q < kPix; ++q) most = max(most, sel_cnt[q]);
+      if (most <= 1u) {                             // block-uniform
+        single = true;
+        break;
+      }
+    }
   }
 
-  // After the last digit, sel_rank is lo's rank among the keys equal to lo and
-  // sel_cnt is how many keys equal lo; rank T/2 still hits lo iff it falls
-  // inside that run, otherwise hi is the smallest key above lo.
-  const unsigned lo_key = sel_prefix[px];
+  // lo: the full key is the prefix after four digits; after an early stop it
+  // is the one key that carries the selected prefix.
+  unsigned lo_key;
+  if (single) {
+    const unsigned prefix = sel_prefix[px];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i)
+      if ((key[i] & mask) == prefix) atomicMin(&sel_lo[px], key[i]);
+    __syncthreads();
+    lo_key = sel_lo[px];
+  } else {
+    lo_key = sel_prefix[px];
+  }
+  // sel_rank is lo's rank among the keys that carry its prefix and sel_cnt
+  // how many keys carry it (after four digits: how many equal lo); rank T/2
+  // still hits lo iff it falls inside that run, otherwise hi is the smallest
+  // key above lo.
   unsigned local_min = 0xFFFFFFFFu;
 #pragma unroll
   for (int i = 0; i < VPT; ++i)
@@ -174,19 +226,17 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   if (resid != nullptr) {
     __syncthreads();
     const float med = sel_med[px];
-    const float* rbase = resid;
+    unsigned long long raddr = reinterpret_cast<unsigned long long>(resid + pix0);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const long long f0 = (long long)kGroups * i;
+      const float r = val_of(key[i]) - med;
       if constexpr (BUF) {
-        const long long nf = T - f0 < kGroups ? T - f0 : kGroups;
-        const long long bytes = nf > 0 ? (nf - 1) * npix * 4 + (npix - pix0) * 4 : 0;
-        const __amdgpu_buffer_rsrc_t r =
-            frames_rsrc(rbase + f0 * npix + pix0, (unsigned)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL));
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), r, (int)voff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(
+            __float_as_int(r), frames_rsrc(reinterpret_cast<const float*>(raddr), group_ext(i)), (int)voff, 0, 0);
+        raddr += gstride;
       } else {
-        const long long t = g + f0;
-        if (pix_ok && t < T) resid[t * npix + pix] = val_of(key[i]) - med;
+        const int t = g + kGroups * i;
+        if (pix_ok && t < Ti) resid[(long long)t * npix + pix] = r;
       }
     }
   }

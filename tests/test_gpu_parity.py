@@ -126,6 +126,28 @@ def test_median_bit_exact(torch_dev, T):
     assert got.tobytes() == ref.tobytes()
 
 
+@pytest.mark.parametrize("T", [2, 37, 64, 1000, 2049])
+def test_median_bit_exact_ragged_and_degenerate(torch_dev, T):
+    """A pixel count that leaves the last block partly empty, pixels whose
+    values are all equal, nearly all equal, or two alternating values, beside
+    pixels of distinct values (which end the select early)."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("median ragged T=%d" % T, flush=True)
+    N = 6
+    rng = np.random.default_rng(100 + T)
+    st = (rng.normal(size=(T, N, N)) * 3 + 50).astype(np.float32)
+    st[:, 0, 0] = 5.0
+    st[:, 0, 1] = 5.0
+    st[T // 3, 0, 1] = 7.0
+    st[:, 0, 2] = np.where(np.arange(T) % 2 == 0, -1.5, 2.5).astype(np.float32)
+    st[:, 0, 3] = np.float32(1e-40)                        # subnormal
+    st[::3, 0, 3] = np.float32(-1e-40)
+    got = G.median(torch.from_numpy(st).to(dev)).cpu().numpy()
+    ref = O.median_f32(st)
+    assert got.tobytes() == ref.tobytes()
+
+
 def test_adi_reduce_parity_config1(torch_dev):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
