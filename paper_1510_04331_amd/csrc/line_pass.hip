@@ -130,6 +130,9 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 #ifndef GRAPHIC_COL_WAVE_LAYOUT
 #define GRAPHIC_COL_WAVE_LAYOUT 0
 #endif
+#ifndef GRAPHIC_COL_STAGED
+#define GRAPHIC_COL_STAGED 1
+#endif
 
 // Thread layout of a pass.  Row passes, and column passes when
 // GRAPHIC_COL_WAVE_LAYOUT is set, keep every job inside one wave (lanes =
@@ -179,20 +182,42 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, un
 
 constexpr unsigned kOOB = 0x80000000u;   // beyond every frame: reads 0, writes dropped
 
+// LDS floats of a block: exchange buffers (or, for staged column blocks, the
+// larger of those and the staging tile of M rows x 2G lines), then the
+// per-job phasor tables.
+template <int M, int KIND, int G, bool STG>
+constexpr int lds_floats() {
+  using S = Shape<M>;
+  constexpr bool LJ = lanes_on_jobs<KIND>() && !STG;
+  constexpr int BUF = G * 2 * S::HALF;
+  constexpr int region = (LJ && col_db<M>()) ? 2 * BUF : BUF;
+  constexpr int stg = STG ? M * (2 * G + 1) : 0;
+  return (region > stg ? region : stg) + 2 * G * S::Ma;
+}
+
 // One block of jobs: frame f, jobs [jb*G, jb*G + G) of that frame.
-template <int M, int KIND, int G, int IO, bool MIR>
+//
+// STG (staged column blocks, canonical window geometry only): every wave owns
+// one job, as in a row block, so the transform's exchanges need only
+// wave-level ordering; the block first copies its 2G source columns (the
+// window rows) into an LDS tile with row-contiguous loads, and writes its
+// results back through the same tile with row-contiguous stores.
+template <int M, int KIND, int G, int IO, bool MIR, bool STG = false>
 __device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
+  static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
   // Column blocks span several waves: their exchanges use separate buffers
   // for real and imaginary parts, so each exchange needs one barrier.  Row
   // blocks are one wave (barriers are free, LDS bounds occupancy): one buffer.
-  constexpr bool LJ = lanes_on_jobs<KIND>();
+  constexpr bool LJ = lanes_on_jobs<KIND>() && !STG;
   constexpr bool DB = LJ && col_db<M>();
   constexpr int BUF = G * 2 * S::HALF;
+  constexpr int SP = 2 * G + 1;                        // staging tile pitch (floats per row)
   extern __shared__ float lds_raw[];
   float* lds = lds_raw;
-  cf* ptab = reinterpret_cast<cf*>(lds_raw + BUF * (DB ? 2 : 1));
+  float* stg = lds_raw;                                // staging tile (aliases the exchange buffers)
+  cf* ptab = reinterpret_cast<cf*>(lds_raw + (lds_floats<M, KIND, G, STG>() - 2 * G * Ma));
 
   const int tid = threadIdx.x;
   int jl, r;
@@ -307,7 +332,54 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const float sg = h ? -1.0f : 1.0f;
   const unsigned tw_lane = (unsigned)(h * M + n1) * 8u;
   cf v[Mb];
-  if constexpr (fast && (IO == kIoWinWin || IO == kIoWinFull)) {
+  // staged blocks: line ranks of the block's 2G lines (slot sl of the tile)
+  auto slot_line = [&](int sl, int& rank, bool& ok, bool dst_side) {
+    const int jj = MIR ? (int)jb * G + (sl < G ? sl : sl - G) : (int)jb * G + (sl >> 1);
+    const bool isb = MIR ? sl >= G : (sl & 1) != 0;
+    int l, lbb;
+    bool bex = true;
+    if (MIR) {
+      l = c - jj;
+      lbb = (c + jj) & (P - 1);
+      bex = (jj != 0) && (lbb != l);
+    } else {
+      l = line_lo + 2 * jj;
+      lbb = l + 1;
+    }
+    const int line = isb ? lbb : l;
+    const int rk = (line - line_lo + P) & (P - 1);
+    ok = jj < p.n_jobs && rk < p.n_lines && (!isb || bex);
+    rank = dst_side ? ((line - (p.dst_line_lo + (p.flip_lines ? flipf : 0)) + P) & (P - 1)) : rk;
+  };
+  if constexpr (STG) {
+    // tile row u = window position u of every line; slot order keeps each
+    // row's global addresses contiguous (mirror pairs: the a lines run
+    // downward from the centre, the b lines upward)
+    {
+      // thread -> fixed slot, rows u0, u0 + JOB/2, ... (2G threads per row)
+      const int sl = tid % (2 * G);
+      int rk;
+      bool ok;
+      slot_line(sl, rk, ok, false);
+      const unsigned lbase = ok ? (unsigned)rk * ls4 : kOOB;
+#pragma unroll 8
+      for (int u = tid / (2 * G); u < M; u += JOB / 2)
+        stg[u * SP + sl] = buf_ld(src, ok ? lbase + (unsigned)(u * ps4) : kOOB);
+    }
+    __syncthreads();
+    const int sa = MIR ? jl : 2 * jl, sb = MIR ? G + jl : 2 * jl + 1;
+#pragma unroll
+    for (int n2 = 0; n2 < Mb; ++n2) {
+      const int k = (n2 + Mb / 2) % Mb;
+      const int ua = n1 + Ma * k;
+      const int ub = MIR ? (Ma - 1 - n1) + Ma * (Mb - 1 - k) : ua;
+      const float av = stg[ua * SP + sa], bv = stg[ub * SP + sb];
+      const float sc = n2 < Mb / 2 ? sg : 1.0f;
+      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
+      v[n2] = cmul({sc * av, sc * bv}, w);
+    }
+    __syncthreads();      // the tile is free: exchanges may overwrite it
+  } else if constexpr (fast && (IO == kIoWinWin || IO == kIoWinFull)) {
     // support [M/2, 3M/2): element m = n1 + Ma n2 has exactly one valid
     // candidate, position u = n1 + Ma ((n2 + Mb/2) mod Mb) of the source line
     const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
@@ -461,6 +533,48 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       for (int n2 = 0; n2 < Mb; ++n2) lds[part * BUF + lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
     xsync();
   }
+  if constexpr (STG) {
+    // half h keeps the window positions of n2 >= Mb/2 (h = 0) or n2 < Mb/2
+    // (h = 1): Mb/2 values per part, held until every wave has left its
+    // exchange buffers, then written through the tile
+    float yv[2][Mb / 2];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      xsync();
+#pragma unroll
+      for (int n2 = 0; n2 < Mb; ++n2) lds[lidx(h, n2, n1)] = part ? v[n2].y : v[n2].x;
+      xsync();
+#pragma unroll
+      for (int q = 0; q < Mb / 2; ++q) {
+        const int n2 = q + (h ? 0 : Mb / 2);
+        const float own = h ? (part ? v[q].y : v[q].x) : (part ? v[q + Mb / 2].y : v[q + Mb / 2].x);
+        yv[part][q] = fmaf(sg, own, lds[lidx(1 - h, n2, n1)]);
+      }
+    }
+    __syncthreads();
+    const int sa = MIR ? jl : 2 * jl, sb = MIR ? G + jl : 2 * jl + 1;
+#pragma unroll
+    for (int q = 0; q < Mb / 2; ++q) {
+      const int n2 = q + (h ? 0 : Mb / 2);
+      const int k = (n2 + Mb / 2) % Mb;
+      const int ua = n1 + Ma * k;
+      const int ub = MIR ? (Ma - 1 - n1) + Ma * (Mb - 1 - k) : ua;
+      stg[ua * SP + sa] = yv[0][q];
+      stg[ub * SP + sb] = yv[1][q];
+    }
+    __syncthreads();
+    {
+      const int sl = tid % (2 * G);
+      int rk;
+      bool ok;
+      slot_line(sl, rk, ok, true);
+      const unsigned lbase = ok ? (unsigned)rk * dls4 : kOOB;
+#pragma unroll 8
+      for (int u = tid / (2 * G); u < M; u += JOB / 2)
+        buf_st(dst, ok ? lbase + (unsigned)(u * dps4) : kOOB, stg[u * SP + sl]);
+    }
+    return;
+  }
 #pragma unroll
   for (int part = 0; part < 2; ++part) {
     if constexpr (!DB) {
@@ -506,6 +620,11 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   }
 }
 
+template <int KIND, int IO>
+constexpr bool staged() {
+  return GRAPHIC_COL_STAGED && KIND == kColPass && IO == kIoWinWin && lanes_on_jobs<KIND>();
+}
+
 // Canonical-geometry and general kernels over a regular grid.  The hardware
 // deals consecutive block ids to the eight XCDs in turn; the remap gives each
 // XCD a contiguous range of blocks, so neighbouring lines share its L2.  When
@@ -523,7 +642,7 @@ line_pass_kernel(const LinePass p) {
   const unsigned jb = lb - f * (unsigned)p.blocks_per_frame;
   if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
     return;   // whole block leaves together, before any barrier
-  process_block<M, KIND, G, IO, MIR>(p, f, jb);
+  process_block<M, KIND, G, IO, MIR, staged<KIND, IO>()>(p, f, jb);
 }
 
 // General path for the half-turned frames listed in p.flip_list (count in
@@ -567,13 +686,11 @@ template <int M, int KIND, int G, int IO, bool MIR>
 static hipError_t launch_g(LinePass p, hipStream_t st) {
   using S = Shape<M>;
   static_assert(G * S::JOB <= 1024, "block too large");
-  static_assert(G * (lanes_on_jobs<KIND>() && col_db<M>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * 4 <= 160 * 1024,
-                "LDS per block above 160 KiB");
+  static_assert(lds_floats<M, KIND, G, staged<KIND, IO>()>() * 4 <= 160 * 1024, "LDS per block above 160 KiB");
   p.blocks_per_frame = (p.n_jobs + G - 1) / G;
   const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const size_t lds =
-      (size_t)G * (lanes_on_jobs<KIND>() && col_db<M>() ? S::PER_JOB_F_DB : S::PER_JOB_F) * sizeof(float);
+  const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
   hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
@@ -581,10 +698,12 @@ static hipError_t launch_g(LinePass p, hipStream_t st) {
   if (e != hipSuccess || IO == kIoGeneric || p.flip == nullptr || !(p.flip_in_off || p.flip_src_reverse))
     return e;
   // half-turned frames: general path over the device-side list
+  const size_t lds_flip = (size_t)lds_floats<M, KIND, G, false>() * sizeof(float);
   hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, MIR>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_flip);
   const long long fb = std::min<long long>(blocks, 2048);
-  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR>), dim3((unsigned)fb), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR>), dim3((unsigned)fb), dim3(G * S::JOB), lds_flip, st,
+                     p);
   return hipGetLastError();
 }
 
