@@ -14,8 +14,9 @@
 // The rank-(T-1)/2 key is found by a most-significant-digit-first radix select
 // with up to four 8-bit digits; each digit builds a 256-bin histogram per
 // pixel in LDS and one wave per pixel scans it.  Every lane of a wave owns a
-// private sub-histogram (pixel, lane group) with two 16-bit counters per word,
-// so the atomic adds of one wave never collide on an address.  The select
+// private sub-histogram (pixel, lane group), so the atomic adds of one wave
+// never collide on an address; keys outside the selected prefix add to a
+// spare slot of their lane's sub-histogram instead of branching around.  The select
 // stops early once every pixel's selected bin holds a single key.  hi is lo
 // itself when at least T/2+1 keys are <= lo, otherwise the smallest key above
 // lo.
@@ -32,7 +33,7 @@ namespace {
 
 constexpr int kGroups = 64;       // frame groups (threads) per pixel
 constexpr int kBins = 256;
-constexpr int kHistWords = kBins / 2 + 1;   // two 16-bit counters per word, +1: distinct banks
+constexpr int kHistWords = kBins + 1;   // 256 bins + 1 slot for keys outside the prefix (odd: spreads banks)
 
 __device__ __forceinline__ unsigned key_of(float v) {
   unsigned b = __float_as_uint(v);
@@ -68,10 +69,8 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
                                                                 float* resid) {
   constexpr int kThreads = kPix * kGroups;
   constexpr int kSub = 64 / kPix;                  // lane groups of one pixel inside a wave
-  // one sub-histogram per (pixel, lane group); a counter sees at most
-  // (waves) x VPT = 1024 keys, so 16 bits suffice
-  static_assert((kThreads / 64) * VPT < 65536, "16-bit histogram counters");
-  __shared__ unsigned hist[kPix * kSub * kHistWords];
+  // one sub-histogram per (pixel, lane group), in dynamic LDS
+  extern __shared__ unsigned hist[];
   __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix], sel_lo[kPix];
   __shared__ float sel_med[kPix];
 
@@ -139,10 +138,8 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
     // (mask = 0 and prefix = 0 for the first digit: every key counts)
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      if ((key[i] & mask) == prefix) {
-        const unsigned bin = (key[i] >> sh) & 0xFFu;
-        atomicAdd(&my_hist[bin >> 1], 1u << ((bin & 1u) << 4));
-      }
+      const unsigned bin = ((key[i] & mask) == prefix) ? ((key[i] >> sh) & 0xFFu) : (unsigned)kBins;
+      atomicAdd(&my_hist[bin], 1u);
     }
     __syncthreads();
     // wave w scans the histogram of pixel w: lane l holds bins l, l+64, l+128, l+192
@@ -156,8 +153,7 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
         const int bin = blk * 64 + lane;
         unsigned x = 0u;
 #pragma unroll
-        for (int q = 0; q < kSub; ++q) x += hist[(w * kSub + q) * kHistWords + (bin >> 1)];
-        x = (bin & 1) ? (x >> 16) : (x & 0xFFFFu);
+        for (int q = 0; q < kSub; ++q) x += hist[(w * kSub + q) * kHistWords + bin];
         const unsigned incl = wave_incl_scan(x);
         const unsigned tot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
         const unsigned long long hit = __ballot(carry + incl > k);
@@ -252,15 +248,21 @@ hipError_t launch_median(const float* stack, long long T, long long npix, float*
   const unsigned blocks = (unsigned)((npix + PIX - 1) / PIX);
   // 32-bit buffer offsets cover 64 frames of the stack when 64 * npix * 4 < 2^31
   const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
-#define GRAPHIC_MEDIAN_CASE(V)                                                                            \
-  if (vpt <= V) {                                                                                        \
-    if (buf)                                                                                             \
-      hipLaunchKernelGGL((median_kernel<V, PIX, true>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, \
-                         npix, out, resid);                                                              \
-    else                                                                                                 \
-      hipLaunchKernelGGL((median_kernel<V, PIX, false>), dim3(blocks), dim3(PIX * kGroups), 0, s, stack, T, \
-                         npix, out, resid);                                                              \
-    return hipGetLastError();                                                                            \
+  const size_t lds = (size_t)PIX * (64 / PIX) * kHistWords * sizeof(unsigned);
+#define GRAPHIC_MEDIAN_CASE(V)                                                                              \
+  if (vpt <= V) {                                                                                          \
+    if (buf) {                                                                                             \
+      hipFuncSetAttribute((const void*)median_kernel<V, PIX, true>,                                        \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      hipLaunchKernelGGL((median_kernel<V, PIX, true>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, T, \
+                         npix, out, resid);                                                                \
+    } else {                                                                                               \
+      hipFuncSetAttribute((const void*)median_kernel<V, PIX, false>,                                       \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      hipLaunchKernelGGL((median_kernel<V, PIX, false>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, \
+                         T, npix, out, resid);                                                             \
+    }                                                                                                      \
+    return hipGetLastError();                                                                              \
   }
   GRAPHIC_MEDIAN_CASE(1)
   GRAPHIC_MEDIAN_CASE(2)
