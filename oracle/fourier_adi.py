@@ -274,18 +274,28 @@ def median_f64(stack):
 # merge).  The reference PSF here is the median of all recentred frames.
 # ---------------------------------------------------------------------------
 
-def adi_reduce(cube, dx, dy, parang_deg, P=None):
-    """Shift, median PSF, subtract, derotate by -parang, median combine.
+def _shift_job(a):
+    return shift(*a)
 
-    Returns a dict with ``final`` (N x N), ``psf`` (N x N), ``shifted`` and
-    ``derotated`` (T x N x N), all float64.
+
+def _rotate_job(a):
+    return rotate(*a)
+
+
+def adi_reduce(cube, dx, dy, parang_deg, P=None, map_fn=map):
+    """Classical ADI (Sect. 3.3 and 3.4): shift every frame, take the median
+    PSF, subtract it, derotate by -parang, median combine.
+
+    ``map_fn`` maps the per-frame operations (the built-in ``map`` by default;
+    a process pool's ``map`` spreads the frames over cores, as the paper's
+    frame-parallel scheme does).  Returns a dict with ``final`` (N x N),
+    ``psf`` (N x N), ``shifted`` and ``derotated`` (T x N x N), all float64.
     """
     cube = np.asarray(cube, dtype=np.float64)
     T, n, _ = cube.shape
-    shifted = np.stack([shift(cube[i], dx[i], dy[i], P) for i in range(T)])
+    shifted = np.stack(list(map_fn(_shift_job, [(cube[i], float(dx[i]), float(dy[i]), P) for i in range(T)])))
     psf = median_f64(shifted)
-    derot = np.stack([rotate(shifted[i] - psf, -float(parang_deg[i]), P)
-                      for i in range(T)])
+    derot = np.stack(list(map_fn(_rotate_job, [(shifted[i] - psf, -float(parang_deg[i]), P) for i in range(T)])))
     final = median_f64(derot)
     return {"final": final, "psf": psf, "shifted": shifted, "derotated": derot}
 

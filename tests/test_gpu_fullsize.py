@@ -1,0 +1,158 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration that
+bench.py times, on sampled outputs the oracle computes one by one.
+
+* SPHERE-like cube, 4096 frames of 1024 x 1024 (padded to 2048): the shift
+  (two passes over the whole cube), the rotation (chunks of 128 frames) and
+  the exact median are checked on sampled frames and pixels; the full ADI
+  reduction is checked through a property that holds at any size (identical
+  frames leave exactly zero residuals and a zero final image).
+* NACO-like cube, 1024 frames of 512 x 512 (padded to 1024): the full ADI
+  reduction against the oracle's, frames spread over a process pool.
+* Uneven cubes of every batch size class (256 ... 2048): one batched call
+  equals one call per cube, bit for bit.
+"""
+
+import multiprocessing as mp
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+FLUX = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def sphere(torch_dev):
+    """The benchmark cube (same generator and seed as bench.py)."""
+    torch, dev = torch_dev
+    p = synth.make_params(3)
+    print("rendering the 4096 x 1024^2 cube", flush=True)
+    cube = synth.render_device(p, dev)
+    torch.cuda.synchronize()
+    yield p, cube
+    del cube
+    torch.cuda.empty_cache()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SAMPLE_FRAMES = (0, 127, 128, 2047, 4095)   # first / last frame of rotation chunks, middle, end
+
+
+def test_shift_full_size(torch_dev, sphere):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    p, cube = sphere
+    print("shift 4096 x 1024^2", flush=True)
+    out = G.shift(cube, p.dx, p.dy)
+    torch.cuda.synchronize()
+    for t in SAMPLE_FRAMES:
+        f = cube[t].cpu().numpy()
+        ref = O.shift(f, p.dx[t], p.dy[t])
+        got = out[t].cpu().numpy()
+        assert _rel(got, ref) <= REL_L2, (t, _rel(got, ref))
+        assert abs(got.astype(np.float64).sum() - ref.sum()) <= FLUX * np.abs(f).sum()
+    del out
+
+
+def test_rotate_full_size(torch_dev, sphere):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    p, cube = sphere
+    print("rotate 4096 x 1024^2", flush=True)
+    out = G.rotate(cube, -p.parang)
+    torch.cuda.synchronize()
+    for t in SAMPLE_FRAMES:
+        f = cube[t].cpu().numpy()
+        ref = O.rotate(f, -p.parang[t])
+        got = out[t].cpu().numpy()
+        assert _rel(got, ref) <= REL_L2, (t, _rel(got, ref))
+        assert abs(got.astype(np.float64).sum() - ref.sum()) <= FLUX * np.abs(f).sum()
+    del out
+
+
+def test_median_full_size(torch_dev, sphere):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    p, cube = sphere
+    print("median 4096 x 1024^2", flush=True)
+    med = G.median(cube).cpu().numpy()
+    rng = np.random.default_rng(7)
+    pix = [(0, 0), (512, 512), (1023, 1023), (0, 1023)] + [tuple(x) for x in rng.integers(0, 1024, size=(60, 2))]
+    ys = torch.tensor([a for a, _ in pix], device=dev)
+    xs = torch.tensor([b for _, b in pix], device=dev)
+    cols = cube[:, ys, xs].cpu().numpy()                     # [T, n_samples]
+    ref = O.median_f32(cols[:, :, None])[:, 0]
+    got = med[[a for a, _ in pix], [b for _, b in pix]]
+    assert got.tobytes() == ref.tobytes()
+
+
+def test_adi_full_size_identical_frames(torch_dev, sphere):
+    """Identical frames with one common shift: every recentred frame equals the
+    PSF, so the residuals and the final image are exactly zero, whatever the
+    angles (the rotation of a zero frame is zero)."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    p, cube = sphere
+    print("adi 4096 x 1024^2, identical frames", flush=True)
+    same = cube[1].expand_as(cube).contiguous()
+    dx = np.full(p.T, 0.37)
+    dy = np.full(p.T, -0.61)
+    fin, psf, res = G.adi_reduce(same, dx, dy, p.parang, psf=True, residuals=True)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(fin)) == 0
+    assert int(torch.count_nonzero(res)) == 0
+    ref = O.shift(cube[1].cpu().numpy(), 0.37, -0.61)
+    assert _rel(psf.cpu().numpy(), ref) <= REL_L2
+    del same, res
+
+
+def test_adi_naco_size_against_oracle(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    p = synth.make_params(2)
+    print("adi 1024 x 512^2 against the oracle", flush=True)
+    cube = synth.render_device(p, dev)
+    fin, psf = G.adi_reduce(cube, p.dx, p.dy, p.parang, psf=True)
+    host = cube.cpu().numpy()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        ref = O.adi_reduce(host, p.dx, p.dy, p.parang, map_fn=lambda f, a: pool.map(f, a, chunksize=8))
+    scale = np.linalg.norm(ref["psf"])
+    assert np.linalg.norm(psf.cpu().numpy() - ref["psf"]) / scale <= REL_L2
+    assert np.linalg.norm(fin.cpu().numpy() - ref["final"]) / scale <= REL_L2
+
+
+def test_batch_every_size_class(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("batch of the four size classes", flush=True)
+    shapes = [(33, 256), (65, 512), (40, 1024), (20, 2048), (7, 256)]
+    cubes, pars = [], []
+    for j, (T, N) in enumerate(shapes):
+        q = synth.make_params(2, seed=synth.BASE_SEED + 200 + j, T=T, N=N)
+        if j % 2:
+            q.parang = np.linspace(-150.0, 150.0, T)       # half-turned frames too
+        cubes.append(synth.render_device(q, dev))
+        pars.append(q)
+    fins = G.adi_reduce_batch(cubes, [q.dx for q in pars], [q.dy for q in pars], [q.parang for q in pars])
+    for c, q, f in zip(cubes, pars, fins):
+        one = G.adi_reduce(c, q.dx, q.dy, q.parang)
+        assert f.cpu().numpy().tobytes() == one.cpu().numpy().tobytes()
