@@ -187,7 +187,33 @@ def bench_batch(args):
     print("batched done", file=sys.stderr, flush=True)
     timed(per_cube, 1)
     tp = timed(per_cube, args.steps)
-    mb, mp = min(tb), min(tp)
+    graph = G.AdiGraph(cubes, dx, dy, pa, inplace=True, workspace=ws)
+    timed(graph.launch, 1)
+    tg = timed(graph.launch, args.steps)
+    graph.close()
+    print("graph done", file=sys.stderr, flush=True)
+    mb, mp, mg = min(tb), min(tp), min(tg)
+
+    # small cube (16 frames of 128^2): host-side cost of one eager call vs one
+    # graph replay, back to back on one stream
+    q = synth.make_params(1)
+    small = torch.from_numpy(synth.render_host(q)).to(dev)
+    sdx, sdy, spa = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (q.dx, q.dy, q.parang))
+    sws = torch.empty(G.batch_workspace_size([small]), dtype=torch.uint8, device=dev)
+    reps = 200
+
+    def per_call(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e6
+    eager_us = per_call(lambda: G.adi_reduce_batch([small], [sdx], [sdy], [spa], workspace=sws))
+    sg = G.AdiGraph([small], [sdx], [sdy], [spa], workspace=sws)
+    graph_us = per_call(sg.launch)
+    sg.close()
     out = {"metric": "frames reduced/s, 64 uneven cubes in one batched call (vs one call per cube)",
            "value": round(frames / mb, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(1e3 * mb, 3), "higher_is_better": True,
@@ -196,6 +222,8 @@ def bench_batch(args):
                                   "in-place full ADI reduction", "frames": frames,
                       "bytes": int(sum(c.numel() for c in cubes) * 4)},
            "per_cube_path": {"value": round(frames / mp, 1), "ms_per_step": round(1e3 * mp, 3)},
+           "graph_replay": {"value": round(frames / mg, 1), "ms_per_step": round(1e3 * mg, 3)},
+           "small_cube_16x128_us_per_reduction": {"eager": round(eager_us, 1), "graph": round(graph_us, 1)},
            "step_ms_all": [round(1e3 * t, 3) for t in tb]}
     print(json.dumps(out), flush=True)
 

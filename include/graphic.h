@@ -207,6 +207,27 @@ graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_
 graphic_status graphic_adi_reduce_batch(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
                                         uint32_t flags, void* ws, size_t ws_bytes, graphic_stream stream);
 
+/* Captured pipelines (HIP graphs).
+ *
+ * graphic_adi_graph_create records every launch that graphic_adi_reduce_batch
+ * would make for these descriptors, workspace and flags into a HIP graph
+ * (stream capture on a library-owned stream), and instantiates it.
+ * graphic_graph_launch replays the whole reduction on `stream` with one call:
+ * same shapes, same device pointers, current contents.  To reduce new data,
+ * write it into the same cube buffers (and parameter arrays) before the
+ * launch.  The caller keeps every buffer named by the descriptors and the
+ * workspace alive and unmoved until graphic_graph_destroy; replays that
+ * overlap on the device race on those buffers.  Errors: the argument checks
+ * of graphic_adi_reduce_batch, made before anything is captured;
+ * GRAPHIC_ERR_HIP if capture or instantiation fails.  Kernel timing is off
+ * inside a captured graph.  The graph holds no memsets. */
+typedef struct graphic_graph_s* graphic_graph;
+
+graphic_status graphic_adi_graph_create(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                        uint32_t flags, void* ws, size_t ws_bytes, graphic_graph* graph);
+graphic_status graphic_graph_launch(graphic_graph graph, graphic_stream stream);
+void graphic_graph_destroy(graphic_graph graph);
+
 /* Per-kernel timing with HIP events on the caller's stream (for benchmarks).
  * When enabled, every library kernel launch is bracketed by events; the
  * accumulated milliseconds and launch counts per kernel family are read with

@@ -19,6 +19,7 @@ EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
     "graphic_median", "graphic_adi_reduce", "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
+    "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
     "graphic_timing_enable", "graphic_timing_read",
 )
 BATCH_INPLACE = 1
@@ -82,6 +83,12 @@ def load():
     lib.graphic_batch_workspace_size.restype = st
     lib.graphic_adi_reduce_batch.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, vp, sz, vp]
     lib.graphic_adi_reduce_batch.restype = st
+    lib.graphic_adi_graph_create.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, vp, sz, ctypes.POINTER(vp)]
+    lib.graphic_adi_graph_create.restype = st
+    lib.graphic_graph_launch.argtypes = [vp, vp]
+    lib.graphic_graph_launch.restype = st
+    lib.graphic_graph_destroy.argtypes = [vp]
+    lib.graphic_graph_destroy.restype = None
     lib.graphic_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.graphic_timing_enable.restype = st
     lib.graphic_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),

@@ -22,6 +22,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -703,6 +704,68 @@ graphic_status graphic_adi_reduce_batch(graphic_ctx ctx, const graphic_cube_desc
                                         uint32_t flags, void* ws, size_t ws_bytes, graphic_stream stream) {
   if (!ctx) return GRAPHIC_ERR_ARG;
   return adi_batch(ctx, descs, n_cubes, flags, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+struct graphic_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+extern "C" {
+
+graphic_status graphic_adi_graph_create(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
+                                        uint32_t flags, void* ws, size_t ws_bytes, graphic_graph* graph) {
+  if (!ctx || !graph) return GRAPHIC_ERR_ARG;
+  *graph = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GRAPHIC_ERR_HIP;
+  const bool timing = ctx->timing;
+  ctx->timing = false;                     // no event nodes inside the graph
+  graphic_status s = GRAPHIC_ERR_HIP;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    s = adi_batch(ctx, descs, n_cubes, flags, ws, ws_bytes, cs);
+    if (hipStreamEndCapture(cs, &g) != hipSuccess && s == GRAPHIC_OK) s = GRAPHIC_ERR_HIP;
+  }
+  ctx->timing = timing;
+  hipStreamDestroy(cs);
+  if (s == GRAPHIC_OK && !g) s = GRAPHIC_ERR_HIP;
+  hipGraphExec_t x = nullptr;
+  if (s == GRAPHIC_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) s = GRAPHIC_ERR_HIP;
+  if (s != GRAPHIC_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  graphic_graph out = new (std::nothrow) graphic_graph_s();
+  if (!out) {
+    hipGraphExecDestroy(x);
+    hipGraphDestroy(g);
+    return GRAPHIC_ERR_NOMEM;
+  }
+  out->graph = g;
+  out->exec = x;
+  out->device = ctx->device;
+  *graph = out;
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_graph_launch(graphic_graph graph, graphic_stream stream) {
+  if (!graph) return GRAPHIC_ERR_ARG;
+  if (hipSetDevice(graph->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  return hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? GRAPHIC_OK
+                                                                                    : GRAPHIC_ERR_HIP;
+}
+
+void graphic_graph_destroy(graphic_graph graph) {
+  if (!graph) return;
+  hipSetDevice(graph->device);
+  if (graph->exec) hipGraphExecDestroy(graph->exec);
+  if (graph->graph) hipGraphDestroy(graph->graph);
+  delete graph;
 }
 
 graphic_status graphic_timing_enable(graphic_ctx ctx, int enable) {

@@ -228,6 +228,57 @@ def adi_reduce_batch(cubes, dx, dy, parang_deg, pad=None, inplace=False, psf=Fal
     return out[0] if len(out) == 1 else tuple(out)
 
 
+class AdiGraph:
+    """A captured batched reduction (HIP graph) over fixed buffers.
+
+    ``cubes``, the parameter tensors, ``finals`` (and ``psfs`` /
+    ``residuals``) and the workspace are bound at capture; ``launch()``
+    replays the whole reduction on the current (or a given) stream with the
+    buffers' current contents.  Write new frames into the same cube tensors
+    (``cube.copy_(...)``) between launches.
+    """
+
+    def __init__(self, cubes, dx, dy, parang_deg, pad=None, inplace=False, psf=False, residuals=False,
+                 workspace=None):
+        import torch
+        self.device = cubes[0].device
+        self.cubes = list(cubes)
+        descs, keep, finals, psfs, resids = _batch_descs(self.cubes, dx, dy, parang_deg, pad, psf, residuals)
+        self._keep = keep
+        self.dx, self.dy, self.parang = keep[0::3], keep[1::3], keep[2::3]
+        self.finals, self.psfs, self.residuals = finals, psfs, resids
+        flags = _abi.BATCH_INPLACE if inplace else 0
+        lib = _abi.load()
+        ctx = context(self.device.index or 0)
+        if workspace is None:
+            n = ctypes.c_size_t()
+            _abi.check(lib.graphic_batch_workspace_size(ctx, descs, len(self.cubes), flags, ctypes.byref(n)),
+                       "graphic_batch_workspace_size")
+            workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        torch.cuda.synchronize(self.device)     # parameter uploads done before capture
+        h = ctypes.c_void_p()
+        _abi.check(lib.graphic_adi_graph_create(ctx, descs, len(self.cubes), flags, _ptr(workspace),
+                                                workspace.numel(), ctypes.byref(h)), "graphic_adi_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        tensors = self.cubes + self._keep + self.finals + self.psfs + self.residuals + [self.workspace]
+        st = _on_stream(stream, self.device, tensors)
+        _abi.check(_abi.load().graphic_graph_launch(self._h, st), "graphic_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _abi.load().graphic_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown
+            pass
+
+
 def timing_enable(enable=True, device_index=0):
     _abi.check(_abi.load().graphic_timing_enable(context(device_index), int(bool(enable))), "graphic_timing_enable")
 
