@@ -142,6 +142,21 @@ def _fill(pools, N):
     return fill
 
 
+def _tune_classes(G, shapes):
+    """Autotune every (median class, size) pair of a workload (before its
+    cubes are allocated: tuning takes a full-size workspace of its own)."""
+    import torch
+    reps = {}
+    for T, N in shapes:
+        key = ((T + 63) // 64 - 1).bit_length(), N
+        reps[key] = max(reps.get(key, 0), T)
+    for (_, N), T in sorted(reps.items()):
+        G.autotune(T, N)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return G.tuning_export()
+
+
 def bench_batch(args):
     import numpy as np
     import torch
@@ -149,6 +164,7 @@ def bench_batch(args):
     import synth
     dev = torch.device("cuda:0")
     ps = synth.make_batch_params(64, with_screen=False)
+    tuning = _tune_classes(G, [(p.T, p.N) for p in ps])
     pools = _pools(torch, dev, [p.N for p in ps])
     cubes = [torch.empty((p.T, p.N, p.N), dtype=torch.float32, device=dev) for p in ps]
     fills = [_fill(pools, p.N) for p in ps]
@@ -223,6 +239,7 @@ def bench_batch(args):
                       "bytes": int(sum(c.numel() for c in cubes) * 4)},
            "per_cube_path": {"value": round(frames / mp, 1), "ms_per_step": round(1e3 * mp, 3)},
            "graph_replay": {"value": round(frames / mg, 1), "ms_per_step": round(1e3 * mg, 3)},
+           "tuning": tuning.strip().split("\n"),
            "small_cube_16x128_us_per_reduction": {"eager": round(eager_us, 1), "graph": round(graph_us, 1)},
            "step_ms_all": [round(1e3 * t, 3) for t in tb]}
     print(json.dumps(out), flush=True)
@@ -238,6 +255,8 @@ def bench_served(args):
     arr = synth.make_arrivals(n, rate=args.rate)
     ps = synth.make_batch_params(n, seed=synth.BASE_SEED + 5, with_screen=False)
     pools = _pools(torch, dev, [p.N for p in ps])
+    import paper_1510_04331_amd as G
+    _tune_classes(G, [(p.T, p.N) for p in ps])
     free_b, total_b = torch.cuda.mem_get_info(dev)
     budget = int(args.budget_gib * 2**30) if args.budget_gib else int(0.6 * free_b)
 
@@ -316,6 +335,8 @@ def main():
     pa = torch.tensor(p.parang, dtype=torch.float64, device=dev)
     nws = G.workspace_size(2, T, N)
     ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+    tuning = G.autotune(T, N, workspace=ws)          # launch shapes for this geometry (ws is scratch here)
+    print("tuning: %s" % tuning.replace("\n", "; "), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     if args.calibrate_copy:
@@ -394,6 +415,7 @@ def main():
                      "unit": "GB/s", "frac": round(fams[dom]["achieved_GBps"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "tuning": tuning.strip().split("\n"),
         "latency_ms": {"p50": round(pct(0.5), 3), "p99": round(pct(0.99), 3)},
         "shift_rotate_frames_per_s": round(T / (sr_ms / 1e3), 1) if sr_ms else None,
         "shift_rotate_hbm_frac": round(56.0 * N * N * (T / (sr_ms / 1e3)) / (HBM_PEAK_GBS * 1e9), 4)

@@ -228,6 +228,34 @@ graphic_status graphic_adi_graph_create(graphic_ctx ctx, const graphic_cube_desc
 graphic_status graphic_graph_launch(graphic_graph graph, graphic_stream stream);
 void graphic_graph_destroy(graphic_graph graph);
 
+/* Autotuning of launch shapes.
+ *
+ * graphic_autotune times the library's alternative launch shapes for a
+ * geometry on the caller's device -- the tile width (jobs per block) of the
+ * column passes for both line pairings, and the pixel tile (16 or 8) of the
+ * median for this frame count -- and keeps the fastest in the context; later
+ * calls with that geometry use them.  Every variant computes bit-identical
+ * results.  It overwrites `ws` with synthetic frames and synchronises
+ * `stream`.  Each kernel is timed at the size of one launch of the pipeline
+ * (the whole cube for the shift's column pass, one rotation chunk for the
+ * y-shear, the whole stack for the median, with and without the residual
+ * rewrite), or on as much of it as `ws` holds; a kernel whose data does not
+ * fit (fewer than 8 frames, or 16384 pixels) keeps its default.  The ADI
+ * workspace of the same geometry (graphic_workspace_size) covers every
+ * kernel at full size.  Errors: GRAPHIC_ERR_ARG / _UNSUPPORTED for the geometry,
+ * GRAPHIC_ERR_WORKSPACE for a null or misaligned `ws`, GRAPHIC_ERR_HIP.
+ *
+ * graphic_tuning_export writes the tuned choices as text (one "col M pairing
+ * variant" or "med class variant" line each) into buf (with its NUL; the
+ * length needed, NUL included, goes to *needed; a short buffer gets a
+ * truncated copy and GRAPHIC_ERR_ARG); graphic_tuning_import reads such text
+ * back (all or nothing: a malformed line leaves the context unchanged and
+ * returns GRAPHIC_ERR_ARG), so that choices can be cached across processes. */
+graphic_status graphic_autotune(graphic_ctx ctx, const graphic_geom* geom, void* ws, size_t ws_bytes,
+                                graphic_stream stream);
+graphic_status graphic_tuning_export(graphic_ctx ctx, char* buf, size_t buf_len, size_t* needed);
+graphic_status graphic_tuning_import(graphic_ctx ctx, const char* text);
+
 /* Per-kernel timing with HIP events on the caller's stream (for benchmarks).
  * When enabled, every library kernel launch is bracketed by events; the
  * accumulated milliseconds and launch counts per kernel family are read with

@@ -5,5 +5,6 @@ C ABI of include/graphic.h; this package only marshals torch tensors to it.
 """
 
 from .ops import (shift, rotate, median, adi_reduce, adi_reduce_batch, workspace_size,  # noqa: F401
-                  batch_workspace_size, AdiGraph, timing_enable, timing_read)
+                  batch_workspace_size, AdiGraph, autotune, tuning_export, tuning_import,
+                  timing_enable, timing_read)
 from ._abi import LIB_PATH, GraphicError  # noqa: F401

@@ -20,6 +20,7 @@ EXPORTS = (
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
     "graphic_median", "graphic_adi_reduce", "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
     "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
+    "graphic_autotune", "graphic_tuning_export", "graphic_tuning_import",
     "graphic_timing_enable", "graphic_timing_read",
 )
 BATCH_INPLACE = 1
@@ -89,6 +90,12 @@ def load():
     lib.graphic_graph_launch.restype = st
     lib.graphic_graph_destroy.argtypes = [vp]
     lib.graphic_graph_destroy.restype = None
+    lib.graphic_autotune.argtypes = [vp, g, vp, sz, vp]
+    lib.graphic_autotune.restype = st
+    lib.graphic_tuning_export.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    lib.graphic_tuning_export.restype = st
+    lib.graphic_tuning_import.argtypes = [vp, ctypes.c_char_p]
+    lib.graphic_tuning_import.restype = st
     lib.graphic_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.graphic_timing_enable.restype = st
     lib.graphic_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),

@@ -1,5 +1,7 @@
 // Small per-frame kernels: rotation parameters and float64 flux sums.
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace graphic {
@@ -58,7 +60,28 @@ __global__ void __launch_bounds__(256) flip_list_kernel(const int* __restrict__ 
   if (threadIdx.x == 0) *count = cnt;
 }
 
+// Values 100 + U(-8, 8) from a counter hash (no state): a sky-like level with
+// noise, written with vector stores only.
+__global__ void __launch_bounds__(256) fill_noise_kernel(float* __restrict__ p, size_t n, unsigned seed) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    unsigned h = (unsigned)i * 0x9E3779B1u ^ seed ^ (unsigned)(i >> 32) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    p[i] = 100.0f + ((float)(h >> 8) * (1.0f / 16777216.0f) - 0.5f) * 16.0f;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_noise_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, seed);
+  return hipGetLastError();
+}
 
 hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* list, int* count, hipStream_t s) {
   hipLaunchKernelGGL(flip_list_kernel, dim3(1), dim3(256), 0, s, flip, f0, n, list, count);

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -64,6 +65,13 @@ struct graphic_ctx_s {
   };
   std::vector<Acc> acc;
   size_t chunk_bytes = kDefaultChunkBytes;
+  // tuned launch variants (-1: not tuned, the default variant 0 runs)
+  int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass
+  int med_var[8];                         // [log2 of the median's values per thread]
+  graphic_ctx_s() {
+    for (auto& a : col_var) a[0] = a[1] = -1;
+    for (int& v : med_var) v = -1;
+  }
 };
 
 namespace {
@@ -199,9 +207,21 @@ struct Timer {
 
 graphic_status hip_ok(hipError_t e) { return e == hipSuccess ? GRAPHIC_OK : GRAPHIC_ERR_HIP; }
 
+int col_variant(graphic_ctx ctx, int P, int mirror) {
+  const int v = ctx->col_var[ilog2(P / 2) & 15][mirror ? 1 : 0];
+  return v < 0 ? 0 : v;
+}
+
+int median_class(long long T) { return ilog2((int)((T + 63) / 64)) & 7; }
+
+int median_variant(graphic_ctx ctx, long long T) {
+  const int v = ctx->med_var[median_class(T)];
+  return v < 0 ? 0 : v;
+}
+
 graphic_status run_pass(graphic_ctx ctx, const LinePass& p, int kind, const char* family, hipStream_t st) {
   Timer t(ctx, st, family);
-  hipError_t e = launch_line_pass(p, kind, 0, st);
+  hipError_t e = launch_line_pass(p, kind, kind == kColPass ? col_variant(ctx, p.P, p.mirror) : 0, st);
   t.done();
   return hip_ok(e);
 }
@@ -397,7 +417,7 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
 graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, float* resid,
                          hipStream_t st) {
   Timer t(ctx, st, "median");
-  hipError_t e = launch_median(stack, T, (long long)N * N, out, resid, st);
+  hipError_t e = launch_median(stack, T, (long long)N * N, out, resid, median_variant(ctx, T), st);
   t.done();
   return hip_ok(e);
 }
@@ -766,6 +786,161 @@ void graphic_graph_destroy(graphic_graph graph) {
   if (graph->exec) hipGraphExecDestroy(graph->exec);
   if (graph->graph) hipGraphDestroy(graph->graph);
   delete graph;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Mean device milliseconds of `reps` back-to-back launches after one warm-up.
+template <class F>
+double time_launches(hipStream_t st, int reps, F&& launch, bool* ok) {
+  hipEvent_t a = nullptr, b = nullptr;
+  *ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+  float ms = 0.f;
+  if (*ok) *ok = launch() == hipSuccess;
+  if (*ok) *ok = hipEventRecord(a, st) == hipSuccess;
+  for (int r = 0; r < reps && *ok; ++r) *ok = launch() == hipSuccess;
+  if (*ok) *ok = hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+                 hipEventElapsedTime(&ms, a, b) == hipSuccess;
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  return (double)ms / reps;
+}
+
+}  // namespace
+
+extern "C" {
+
+graphic_status graphic_autotune(graphic_ctx ctx, const graphic_geom* geom, void* ws, size_t ws_bytes,
+                                graphic_stream stream) {
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  int P = 0;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (geom->n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return GRAPHIC_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int N = geom->n, o = (P - N) / 2;
+  const long long T = geom->n_frames;
+  float* buf = static_cast<float*>(ws);
+  // synthetic frames: the timings do not depend on the values, but the
+  // median's early stop does, so the data is spread like sky frames
+  if (launch_fill_noise(buf, ws_bytes / sizeof(float), 0x2545F491u, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+  bool ok = true;
+  // staged column passes of both pairings (only the canonical geometry has a
+  // second variant), over as many frames as one launch of the pipeline
+  // takes: the whole cube for the shift's y-pass, one rotation chunk for the
+  // y-shear (the tile choice depends on the launch size through its tail)
+  if (P == 2 * N && P / 2 >= 256) {
+    for (int mir = 0; mir < 2; ++mir) {
+      const size_t fb = (size_t)N * (mir ? P : N) * sizeof(float);
+      long long F = std::min<long long>(T, (long long)(ws_bytes / fb));
+      if (mir) F = std::min<long long>(F, std::max<long long>(1, (long long)(ctx->chunk_bytes / fb)));
+      if (F < std::min<long long>(T, 8)) continue;
+      LinePass c = base_pass(ctx, P);
+      c.src = buf;
+      c.dst = buf;
+      c.src_fs = c.dst_fs = (long long)N * (mir ? P : N);
+      c.src_ls = c.dst_ls = 1;
+      c.src_ps = c.dst_ps = mir ? P : N;
+      c.line_lo = mir ? 0 : o;
+      c.n_lines = mir ? P : N;
+      c.in_off = o;
+      c.in_len = N;
+      c.out_off = o;
+      c.out_len = N;
+      c.dst_line_lo = mir ? 0 : o;
+      c.mirror = mir;
+      c.n_jobs = mir ? P / 2 + 1 : N / 2;
+      c.n_frames = F;
+      double best = 0.0;
+      int pick = 0;
+      for (int v = 0; v < 2 && ok; ++v) {
+        const double ms = time_launches(st, 3, [&] { return launch_line_pass(c, kColPass, v, st); }, &ok);
+        if (ok && (v == 0 || ms < best)) {
+          best = ms;
+          pick = v;
+        }
+      }
+      if (!ok) return GRAPHIC_ERR_HIP;
+      ctx->col_var[ilog2(P / 2)][mir] = pick;
+    }
+  }
+  // median: the pipeline runs it twice per cube, once rewriting the stack as
+  // residuals and once read-only; both are timed, on as many pixels of this
+  // frame count as the workspace holds
+  long long npix = std::min<long long>((long long)N * N, (long long)(ws_bytes / sizeof(float)) / (T + 1));
+  npix -= npix % 128;
+  if (npix >= std::min<long long>(16384, (long long)N * N - ((long long)N * N) % 128)) {
+    float* out = buf + (size_t)T * npix;
+    double best = 0.0;
+    int pick = 0;
+    for (int v = 0; v < 2 && ok; ++v) {
+      const double ms = time_launches(st, 2, [&] {
+        hipError_t e = launch_median(buf, T, npix, out, buf, v, st);
+        return e != hipSuccess ? e : launch_median(buf, T, npix, out, nullptr, v, st);
+      }, &ok);
+      if (ok && (v == 0 || ms < best)) {
+        best = ms;
+        pick = v;
+      }
+    }
+    if (!ok) return GRAPHIC_ERR_HIP;
+    ctx->med_var[median_class(T)] = pick;
+  }
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_tuning_export(graphic_ctx ctx, char* buf, size_t buf_len, size_t* needed) {
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  std::string t;
+  for (int l = 0; l < 16; ++l)
+    for (int m = 0; m < 2; ++m)
+      if (ctx->col_var[l][m] >= 0)
+        t += "col " + std::to_string(1 << l) + " " + std::to_string(m) + " " + std::to_string(ctx->col_var[l][m]) + "\n";
+  for (int c = 0; c < 8; ++c)
+    if (ctx->med_var[c] >= 0) t += "med " + std::to_string(c) + " " + std::to_string(ctx->med_var[c]) + "\n";
+  if (needed) *needed = t.size() + 1;
+  if (buf && buf_len > 0) {
+    const size_t n = std::min(buf_len - 1, t.size());
+    std::memcpy(buf, t.data(), n);
+    buf[n] = '\0';
+    if (buf_len < t.size() + 1) return GRAPHIC_ERR_ARG;
+  }
+  return GRAPHIC_OK;
+}
+
+graphic_status graphic_tuning_import(graphic_ctx ctx, const char* text) {
+  if (!ctx || !text) return GRAPHIC_ERR_ARG;
+  int col[16][2], med[8];
+  std::memcpy(col, ctx->col_var, sizeof(col));
+  std::memcpy(med, ctx->med_var, sizeof(med));
+  const char* q = text;
+  while (*q) {
+    while (*q == '\n' || *q == ' ') ++q;
+    if (!*q) break;
+    char kind[4] = {0};
+    int a = 0, b = 0, v = 0, used = 0;
+    if (std::sscanf(q, "%3s %d %d %d%n", kind, &a, &b, &v, &used) == 4 && std::strcmp(kind, "col") == 0) {
+      if (a < 8 || a > 2048 || (a & (a - 1)) || (b != 0 && b != 1) || v < 0 || v > 1) return GRAPHIC_ERR_ARG;
+      col[ilog2(a)][b] = v;
+    } else if (std::sscanf(q, "%3s %d %d%n", kind, &a, &v, &used) == 3 && std::strcmp(kind, "med") == 0) {
+      if (a < 0 || a > 7 || v < 0 || v > 1) return GRAPHIC_ERR_ARG;
+      med[a] = v;
+    } else {
+      return GRAPHIC_ERR_ARG;
+    }
+    q += used;
+    while (*q && *q != '\n') {
+      if (*q != ' ') return GRAPHIC_ERR_ARG;
+      ++q;
+    }
+  }
+  std::memcpy(ctx->col_var, col, sizeof(col));
+  std::memcpy(ctx->med_var, med, sizeof(med));
+  return GRAPHIC_OK;
 }
 
 graphic_status graphic_timing_enable(graphic_ctx ctx, int enable) {

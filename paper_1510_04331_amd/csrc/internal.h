@@ -81,7 +81,9 @@ enum PassKind { kRowPass = 0, kColPass = 1 };
 // Index patterns of a pass (input support -> output window), see line_pass.hip.
 enum IoKind { kIoGeneric = 0, kIoWinWin = 1, kIoWinFull = 2, kIoFullWin = 3 };
 
-hipError_t launch_line_pass(const LinePass& p, int kind, int jobs_per_block, hipStream_t s);
+// variant: 0 = default launch shape; 1 = the alternative tile width of the
+// staged column pass (rows and other geometries ignore it).
+hipError_t launch_line_pass(const LinePass& p, int kind, int variant, hipStream_t s);
 
 // Per-frame rotation parameters from angles: flip (|theta| > 90), -tan(theta'/2), sin(theta').
 hipError_t launch_rotation_params(const double* theta_deg, double sign, long long T,
@@ -95,8 +97,12 @@ hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* lis
 
 // Exact per-pixel median of a [T][npix] stack -> [npix]; with resid non-null,
 // every value is also written back as value - median (resid may be stack).
+// variant: 0 = 16-pixel tiles, 1 = 8-pixel tiles (same result).
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
-                         hipStream_t s);
+                         int variant, hipStream_t s);
+
+// n floats of seeded noise around a sky level (for timing runs on scratch).
+hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
 
 // Per-frame float64 sums of [T][N][N] frames into flux[2*t + slot].
 hipError_t launch_frame_sums(const float* frames, long long T, int N, double* flux, int slot,

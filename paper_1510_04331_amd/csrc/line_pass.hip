@@ -744,25 +744,39 @@ static hipError_t launch_io(const LinePass& p, hipStream_t st) {
   return launch_g<M, KIND, G, kIoGeneric, true>(p, st);
 }
 
+// Alternative tile width (jobs per block) of the staged column pass per M,
+// offered to the autotuner as variant 1.
 template <int M>
-static hipError_t launch_m(const LinePass& p, int kind, hipStream_t st) {
+constexpr int col_jobs_alt() {
+  return M == 256 ? 8 : M == 512 ? 16 : M == 1024 ? 4 : M == 2048 ? 4 : 0;
+}
+
+template <int M>
+static hipError_t launch_m(const LinePass& p, int kind, int variant, hipStream_t st) {
   if (kind == kRowPass) return launch_io<M, kRowPass, row_jobs_per_block<M>()>(p, st);
+  constexpr int GA = col_jobs_alt<M>();
+  if constexpr (GA > 0 && GRAPHIC_COL_STAGED && lanes_on_jobs<kColPass>()) {
+    if (variant == 1 && io_kind(p) == kIoWinWin) {
+      return p.mirror ? launch_g<M, kColPass, GA, kIoWinWin, true>(p, st)
+                      : launch_g<M, kColPass, GA, kIoWinWin, false>(p, st);
+    }
+  }
   return launch_io<M, kColPass, col_jobs_per_block<M>()>(p, st);
 }
 
-hipError_t launch_line_pass(const LinePass& p, int kind, int /*jobs_per_block*/, hipStream_t s) {
+hipError_t launch_line_pass(const LinePass& p, int kind, int variant, hipStream_t s) {
   const long long total = p.n_frames * (long long)p.n_jobs;
   if (total <= 0) return hipSuccess;
   switch (p.P / 2) {
-    case 8: return launch_m<8>(p, kind, s);
-    case 16: return launch_m<16>(p, kind, s);
-    case 32: return launch_m<32>(p, kind, s);
-    case 64: return launch_m<64>(p, kind, s);
-    case 128: return launch_m<128>(p, kind, s);
-    case 256: return launch_m<256>(p, kind, s);
-    case 512: return launch_m<512>(p, kind, s);
-    case 1024: return launch_m<1024>(p, kind, s);
-    case 2048: return launch_m<2048>(p, kind, s);
+    case 8: return launch_m<8>(p, kind, variant, s);
+    case 16: return launch_m<16>(p, kind, variant, s);
+    case 32: return launch_m<32>(p, kind, variant, s);
+    case 64: return launch_m<64>(p, kind, variant, s);
+    case 128: return launch_m<128>(p, kind, variant, s);
+    case 256: return launch_m<256>(p, kind, variant, s);
+    case 512: return launch_m<512>(p, kind, variant, s);
+    case 1024: return launch_m<1024>(p, kind, variant, s);
+    case 2048: return launch_m<2048>(p, kind, variant, s);
     default: return hipErrorInvalidValue;
   }
 }

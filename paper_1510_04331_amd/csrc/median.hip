@@ -7,9 +7,10 @@
 // of rank (T-1)/2, hi the element of rank T/2, and the median is
 // (lo + hi) * 0.5 in float32.
 //
-// Layout: a block of 1024 threads owns 16 consecutive pixels and all T values
-// of each (16 waves; lanes = 16 pixels x 4 frame groups, so every load reads
-// 64 contiguous bytes of one frame).  Thread (pixel, g) keeps the keys of
+// Layout: a block owns kPix consecutive pixels (16, or 8 as the tuned
+// alternative) and all T values of each (kPix waves; lanes = kPix pixels x
+// 64/kPix frame groups, so every load reads 4 kPix contiguous bytes of a
+// frame).  Thread (pixel, g) keeps the keys of
 // frames g, g+64, g+128, ... in registers, so the stack is read from HBM once.
 // The rank-(T-1)/2 key is found by a most-significant-digit-first radix select
 // with up to four 8-bit digits; each digit builds a 256-bin histogram per
@@ -22,10 +23,6 @@
 // lo.
 
 #include "internal.h"
-
-#ifndef GRAPHIC_MEDIAN_PIX
-#define GRAPHIC_MEDIAN_PIX 16
-#endif
 
 namespace graphic {
 
@@ -240,11 +237,10 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
 
 }  // namespace
 
-hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
-                         hipStream_t s) {
-  if (T <= 0 || npix <= 0) return hipSuccess;
+template <int PIX>
+static hipError_t launch_median_pix(const float* stack, long long T, long long npix, float* out, float* resid,
+                                    hipStream_t s) {
   const long long vpt = (T + kGroups - 1) / kGroups;
-  constexpr int PIX = GRAPHIC_MEDIAN_PIX;
   const unsigned blocks = (unsigned)((npix + PIX - 1) / PIX);
   // 32-bit buffer offsets cover 64 frames of the stack when 64 * npix * 4 < 2^31
   const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
@@ -273,6 +269,13 @@ hipError_t launch_median(const float* stack, long long T, long long npix, float*
   GRAPHIC_MEDIAN_CASE(64)
 #undef GRAPHIC_MEDIAN_CASE
   return hipErrorInvalidValue;   // T > 4096: rejected on the host before launch
+}
+
+hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid, int variant,
+                         hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  return variant == 1 ? launch_median_pix<8>(stack, T, npix, out, resid, s)
+                      : launch_median_pix<16>(stack, T, npix, out, resid, s);
 }
 
 }  // namespace graphic

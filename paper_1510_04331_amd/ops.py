@@ -279,6 +279,38 @@ class AdiGraph:
             pass
 
 
+def autotune(T, N, pad=None, device_index=0, workspace=None):
+    """Time the alternative launch shapes for this geometry and keep the
+    fastest in the device's context (returns the tuning text)."""
+    import torch
+    dev = torch.device("cuda", device_index)
+    P = _abi.load().graphic_resolved_pad(ctypes.byref(_geom(T, N, pad)))
+    if P < 0:
+        raise ValueError("unsupported geometry T=%d N=%d pad=%s" % (T, N, pad))
+    if workspace is None:
+        workspace = torch.empty(max(workspace_size(_abi.OP_ADI, T, N, pad, device_index), 256),
+                                dtype=torch.uint8, device=dev)
+    g = _geom(T, N, pad)
+    _abi.check(_abi.load().graphic_autotune(context(device_index), ctypes.byref(g), _ptr(workspace),
+                                            workspace.numel(), _stream(dev)), "graphic_autotune")
+    return tuning_export(device_index)
+
+
+def tuning_export(device_index=0):
+    lib = _abi.load()
+    need = ctypes.c_size_t()
+    _abi.check(lib.graphic_tuning_export(context(device_index), None, 0, ctypes.byref(need)),
+               "graphic_tuning_export")
+    buf = ctypes.create_string_buffer(need.value)
+    _abi.check(lib.graphic_tuning_export(context(device_index), buf, need.value, ctypes.byref(need)),
+               "graphic_tuning_export")
+    return buf.value.decode()
+
+
+def tuning_import(text, device_index=0):
+    _abi.check(_abi.load().graphic_tuning_import(context(device_index), text.encode()), "graphic_tuning_import")
+
+
 def timing_enable(enable=True, device_index=0):
     _abi.check(_abi.load().graphic_timing_enable(context(device_index), int(bool(enable))), "graphic_timing_enable")
 
