@@ -27,6 +27,9 @@ import time
 
 METRIC = "frames shifted+rotated/s at 1024² FP32 (% HBM roofline); cube p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed instructions (which these kernels are built
+# without): 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -71,8 +74,22 @@ def alg_bytes_per_frame(fam, N, P, T):
         "shear_x1": n2 + nP,
         "shear_y": 2 * nP,
         "shear_x2": nP + n2,
-        "median": n2 + n2 / T,
+        # both medians of a step, per frame: the PSF median reads the stack and
+        # writes it back as residuals, the final one reads it (plus one image
+        # each); bench.py averages them over the step's two launches
+        "median": 3 * n2 + 2 * n2 / T,
     }.get(fam)
+
+
+# Nominal flops per frame of each line pass: every job is two real lines
+# packed in one complex line, transformed forward and back at length P
+# (5 P log2 P flops per complex transform).
+def alg_flops_per_frame(fam, N, P):
+    pairs = {"shift_y": N // 2, "shift_x": N // 2, "shear_x1": N // 2, "shear_y": P // 2,
+             "shear_x2": N // 2}.get(fam)
+    if pairs is None:
+        return None
+    return pairs * 2 * 5 * P * math.log2(P)
 
 
 FAMILIES = ("shift_y", "shift_x", "shear_x1", "shear_y", "shear_x2", "median", "aux")
@@ -284,6 +301,22 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def roofline(d, fam, traffic):
+    """The dominant kernel against its bound: the line passes are limited by
+    the FP32 vector units (nominal FFT flops against the non-packed peak),
+    the median by HBM.  The HBM fraction of a line pass is reported beside."""
+    hbm = {"hbm_achieved_GBps": round(d["achieved_GBps"], 1),
+           "hbm_frac": round(d["achieved_GBps"] / HBM_PEAK_GBS, 4)}
+    if "achieved_TFLOPs" in d:
+        r = {"bound": "alu", "kernel": fam, "achieved": round(d["achieved_TFLOPs"], 2),
+             "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+             "frac": round(d["achieved_TFLOPs"] / ALU_PEAK_TFLOPS, 4), "traffic": traffic}
+        r.update(hbm)
+        return r
+    return {"bound": "hbm", "kernel": fam, "achieved": hbm["hbm_achieved_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": hbm["hbm_frac"], "traffic": traffic}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +326,8 @@ def main():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("adi", "batch", "served"), default="adi")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip autotuning (default launch shapes; keeps tuning launches out of profiles)")
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--slots", type=int, default=4)
@@ -335,7 +370,7 @@ def main():
     pa = torch.tensor(p.parang, dtype=torch.float64, device=dev)
     nws = G.workspace_size(2, T, N)
     ws = torch.empty(nws, dtype=torch.uint8, device=dev)
-    tuning = G.autotune(T, N, workspace=ws)          # launch shapes for this geometry (ws is scratch here)
+    tuning = "" if args.no_tune else G.autotune(T, N, workspace=ws)   # launch shapes (ws is scratch here)
     print("tuning: %s" % tuning.replace("\n", "; "), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
@@ -383,6 +418,10 @@ def main():
         frames_per_launch = T / d["launches_per_step"]
         d["alg_bytes_per_launch"] = b * frames_per_launch
         d["achieved_GBps"] = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
+        fl = alg_flops_per_frame(fam, N, P)
+        if fl is not None:
+            d["alg_flops_per_launch"] = fl * frames_per_launch
+            d["achieved_TFLOPs"] = d["alg_flops_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e12
     dom = max((f for f in fams if "achieved_GBps" in fams[f]), key=lambda f: fams[f]["ms_per_step"])
     traffic = None
     per_frame = read_traffic(args.traffic, dom, N, P)
@@ -410,12 +449,9 @@ def main():
                                "reduction (shift, median PSF, subtract, derotate, median combine)"
                                % (T, N, N, P, P),
                    "frames": T, "size": N, "pad": P, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom,
-                     "achieved": round(fams[dom]["achieved_GBps"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(fams[dom]["achieved_GBps"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+        "roofline": roofline(fams[dom], dom, traffic),
         "cpu_baseline": cpu,
-        "tuning": tuning.strip().split("\n"),
+        "tuning": tuning.strip().split("\n") if tuning else "defaults",
         "latency_ms": {"p50": round(pct(0.5), 3), "p99": round(pct(0.99), 3)},
         "shift_rotate_frames_per_s": round(T / (sr_ms / 1e3), 1) if sr_ms else None,
         "shift_rotate_hbm_frac": round(56.0 * N * N * (T / (sr_ms / 1e3)) / (HBM_PEAK_GBS * 1e9), 4)
