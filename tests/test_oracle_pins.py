@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import synth
 
 
 def _blobs(n, centres, sigma=3.0, amps=None):
@@ -284,3 +285,81 @@ def test_adi_recovers_companion_position():
     w = np.clip(fin, 0, None) * (np.hypot(xx - x, yy - y) < 3)
     cx, cy = (w * xx).sum() / w.sum(), (w * yy).sum() / w.sum()
     assert math.hypot(cx - (c + p0[0]), cy - (c + p0[1])) < 0.5
+
+
+# ---------------------------------------------------------------------------
+# Per-frame PSF selection (Sect. 3.3: time separation below t_max, field
+# rotation above alpha_min)
+# ---------------------------------------------------------------------------
+
+def test_alpha_min_chord_angle():
+    # a point at radius 10 px moving 2 x 4 px along its arc: chord 8 px -> 2 arcsin(0.4)
+    assert abs(O.alpha_min_deg(2, 4.0, 10.0) - 47.15635696) < 1e-6
+    assert O.alpha_min_deg(0, 4.0, 10.0) == 0.0
+    # small-angle limit: the arc length n FWHM / r_min radians
+    assert abs(O.alpha_min_deg(1, 0.01, 100.0) - np.degrees(1e-4)) < 1e-10
+
+
+def test_select_frames_by_hand():
+    # frames every 1 s, 2 degrees apart: frame i takes k with |k - i| < 3.5 and 2|k - i| > 3
+    t = np.arange(8.0)
+    a = 2.0 * np.arange(8.0)
+    sel = O.select_frames(t, a, 3.5, 3.0)
+    for i in range(8):
+        want = {k for k in range(8) if 2 <= abs(k - i) <= 3}
+        assert set(np.flatnonzero(sel[i])) == want, i
+    # nothing rotates enough: every frame falls back to all frames
+    sel = O.select_frames(t, np.zeros(8), 10.0, 1.0)
+    assert sel.all()
+
+
+def test_window_median_brute_force():
+    rng = np.random.default_rng(12)
+    st = rng.normal(size=(11, 3, 4)).astype(np.float32)
+    st[:, 0, 0] = 1.0                                   # ties
+    sel = rng.random((11, 11)) < 0.5
+    sel[3] = False
+    sel[3, 5] = True                                    # a single frame
+    got = O.median_window_f32(st, sel)
+    for i in range(11):
+        vals = np.sort(st[sel[i]].astype(np.float64), axis=0)
+        K = vals.shape[0]
+        want = ((vals[(K - 1) // 2] + vals[K // 2]) * 0.5).astype(np.float32)
+        assert np.array_equal(got[i], want)
+    assert np.array_equal(got[3], st[5])
+
+
+def test_window_reduces_to_classical_adi():
+    """With no time limit and a negative minimum rotation every frame selects
+    all frames, and the reduction is the classical one."""
+    p = synth.make_params(1, T=8, N=32)
+    cube = synth.render_host(p)
+    t = np.arange(p.T, dtype=np.float64)
+    a = O.adi_reduce(cube, p.dx, p.dy, p.parang)
+    b = O.adi_reduce_window(cube, p.dx, p.dy, p.parang, t, np.inf, -1.0)
+    assert np.array_equal(b["psf"][3], a["psf"])
+    assert np.allclose(b["final"], a["final"], rtol=0, atol=1e-12 * np.abs(a["psf"]).max())
+
+
+def test_window_adi_keeps_more_companion_flux():
+    """The selection keeps frames where the companion sits at the same place
+    out of its PSF, so less of it is subtracted than with the all-frames PSF
+    (the motivation of the per-frame PSF in Sect. 3.3)."""
+    T, N = 24, 48
+    ang = np.linspace(0.0, 120.0, T)
+    yy, xx = np.mgrid[0:N, 0:N]
+    c = N / 2.0
+    cube = np.zeros((T, N, N))
+    for i in range(T):
+        cube[i] += 100.0 * np.exp(-((xx - c) ** 2 + (yy - c) ** 2) / (2 * 3.0 ** 2))
+        th = np.radians(ang[i])
+        px, py = c + 10.0 * np.cos(th), c + 10.0 * np.sin(th)
+        cube[i] += 5.0 * np.exp(-((xx - px) ** 2 + (yy - py) ** 2) / (2 * 1.5 ** 2))
+    z = np.zeros(T)
+    t = np.arange(T, dtype=np.float64)
+    amin = O.alpha_min_deg(1.5, 3.5, 10.0)
+    w = O.adi_reduce_window(cube.astype(np.float32), z, z, ang, t, 100.0, amin)
+    a = O.adi_reduce(cube.astype(np.float32), z, z, ang)
+    ref = (int(round(c)), int(round(c + 10)))              # companion at angle 0 after derotation
+    assert w["final"][ref[0], ref[1]] > a["final"][ref[0], ref[1]]
+    assert w["final"][ref[0], ref[1]] > 0.6 * 5.0
