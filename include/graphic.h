@@ -78,7 +78,9 @@ enum {
     GRAPHIC_OP_SHIFT = 0,
     GRAPHIC_OP_ROTATE = 1,
     GRAPHIC_OP_ADI = 2,
-    GRAPHIC_OP_MEDIAN = 3
+    GRAPHIC_OP_MEDIAN = 3,
+    GRAPHIC_OP_MEDIAN_WINDOW = 4,
+    GRAPHIC_OP_ADI_WINDOW = 5
 };
 
 /* Geometry of one cube. */
@@ -169,6 +171,43 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
                                   const double* parang_deg, float* final_img,
                                   float* psf, float* residuals,
                                   void* ws, size_t ws_bytes, graphic_stream stream);
+
+/*
+ * Per-frame PSF with the frame selection of Sect. 3.3: the PSF of frame i is
+ * the median (as in graphic_median) of the frames k with
+ *   |times_k - times_i| < t_max   and   |parang_k - parang_i| > alpha_min_deg,
+ * and a frame whose selection is empty takes the median of all frames.  (The
+ * paper prints the minimum rotation as 2 sin(n FWHM / (2 r_min)); callers
+ * derive alpha_min_deg as the chord angle 2 arcsin(n FWHM / (2 r_min)).)
+ * Frame i never selects itself unless alpha_min_deg < 0 or the fallback applies.
+ *   stack     : [T][N][N] float32, T <= 2048.
+ *   times     : [T] float64 observing times (any unit, the unit of t_max).
+ *   parang_deg: [T] float64 parallactic angles.
+ *   psf_cube  : NULL or [T][N][N] float32, receives PSF_i.
+ *   resid     : NULL or [T][N][N] float32, receives stack_i - PSF_i (may be
+ *               stack itself; otherwise it must not overlap it).  At least
+ *               one of psf_cube and resid is given.
+ *   ws        : graphic_workspace_size(GRAPHIC_OP_MEDIAN_WINDOW) bytes (the
+ *               selection: T x 512 bytes plus T ints).
+ * Cost: one select per frame over its selected frames, O(T^2 N^2).
+ */
+graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, const float* stack,
+                                     const double* times, const double* parang_deg, double t_max,
+                                     double alpha_min_deg, float* psf_cube, float* resid,
+                                     void* ws, size_t ws_bytes, graphic_stream stream);
+
+/*
+ * ADI reduction with the per-frame PSF of graphic_median_window:
+ * S_i = shift(cube_i), R_i = S_i - PSF_i, D_i = rotate(R_i, -parang_i),
+ * final = median_i D_i.  Arguments as graphic_adi_reduce, plus the selection
+ * (times, t_max, alpha_min_deg) and psf_cube (NULL or [T][N][N]).  T <= 2048.
+ *   ws : graphic_workspace_size(GRAPHIC_OP_ADI_WINDOW) bytes.
+ */
+graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
+                                         const double* dx, const double* dy, const double* parang_deg,
+                                         const double* times, double t_max, double alpha_min_deg,
+                                         float* final_img, float* psf_cube, float* residuals,
+                                         void* ws, size_t ws_bytes, graphic_stream stream);
 
 /*
  * Batched ADI reduction of cubes of uneven frame count and size (the

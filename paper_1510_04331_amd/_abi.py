@@ -12,13 +12,14 @@ LIB_PATH = os.path.join(HERE, "libgraphic.so")
 
 # status codes (graphic_status)
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM = range(6)
-OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN = range(4)
+OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN, OP_MEDIAN_WINDOW, OP_ADI_WINDOW = range(6)
 
 # every symbol that include/graphic.h declares
 EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
-    "graphic_median", "graphic_adi_reduce", "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
+    "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_adi_reduce_window",
+    "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
     "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
     "graphic_autotune", "graphic_tuning_export", "graphic_tuning_import",
     "graphic_timing_enable", "graphic_timing_read",
@@ -79,6 +80,11 @@ def load():
     lib.graphic_median.restype = st
     lib.graphic_adi_reduce.argtypes = [vp, g, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.graphic_adi_reduce.restype = st
+    f64 = ctypes.c_double
+    lib.graphic_median_window.argtypes = [vp, g, vp, vp, vp, f64, f64, vp, vp, vp, sz, vp]
+    lib.graphic_median_window.restype = st
+    lib.graphic_adi_reduce_window.argtypes = [vp, g, vp, vp, vp, vp, vp, f64, f64, vp, vp, vp, vp, sz, vp]
+    lib.graphic_adi_reduce_window.restype = st
     cd = ctypes.POINTER(CubeDesc)
     lib.graphic_batch_workspace_size.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)]
     lib.graphic_batch_workspace_size.restype = st

@@ -35,6 +35,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxT_Median = 4096;
+constexpr int kMaxT_Window = 2048;      // the per-frame median keeps a median per held frame in registers
 constexpr size_t kDefaultChunkBytes = size_t(1) << 30;   // rotation scratch per chunk
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -146,6 +147,10 @@ graphic_status check_geom(const graphic_geom* g, int* P_out) {
   if (!is_pow2(P) || P < g->n || P < 2 * kMinM || P > 2 * kMaxM) return g->pad ? GRAPHIC_ERR_ARG : GRAPHIC_ERR_UNSUPPORTED;
   *P_out = P;
   return GRAPHIC_OK;
+}
+
+size_t window_sel_bytes(long long T) {
+  return align_up((size_t)T * 64 * sizeof(unsigned long long)) + align_up((size_t)T * sizeof(int));
 }
 
 bool overlap_bad(const void* a, const void* b, size_t bytes) {
@@ -625,6 +630,12 @@ graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geo
       return GRAPHIC_OK;
     }
     case GRAPHIC_OP_MEDIAN: *bytes = 0; return T > kMaxT_Median ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+    case GRAPHIC_OP_MEDIAN_WINDOW:
+      *bytes = window_sel_bytes(T);
+      return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+    case GRAPHIC_OP_ADI_WINDOW:
+      *bytes = align_up((size_t)T * N * N * sizeof(float)) + window_sel_bytes(T) + rot_layout(T, N, P, chunk, 0).total;
+      return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
     default: return GRAPHIC_ERR_ARG;
   }
 }
@@ -708,6 +719,98 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, con
   d.psf = psf;
   d.residuals = residuals;
   return adi_batch(ctx, &d, 1, 0u, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+graphic_status window_args(graphic_ctx ctx, const graphic_geom* geom, const void* times, const void* parang,
+                           double t_max, double alpha_min, int* P) {
+  if (!ctx || !geom || !times || !parang) return GRAPHIC_ERR_ARG;
+  graphic_status s = check_geom(geom, P);
+  if (s != GRAPHIC_OK) return s;
+  if (geom->n_frames > kMaxT_Window) return GRAPHIC_ERR_UNSUPPORTED;
+  if (std::isnan(t_max) || std::isnan(alpha_min)) return GRAPHIC_ERR_ARG;
+  return GRAPHIC_OK;
+}
+
+// Selection, then the per-frame medians (Sect. 3.3); sel_ws holds the
+// selection rows and counts.
+graphic_status do_median_window(graphic_ctx ctx, long long T, int N, const float* stack, const double* times,
+                                const double* parang, double t_max, double alpha_min, float* psf, float* resid,
+                                char* sel_ws, hipStream_t st) {
+  auto* sel = reinterpret_cast<unsigned long long*>(sel_ws);
+  auto* counts = reinterpret_cast<int*>(sel_ws + align_up((size_t)T * 64 * sizeof(unsigned long long)));
+  Timer t(ctx, st, "median");
+  hipError_t e = launch_select_frames(times, parang, T, t_max, alpha_min, sel, counts, st);
+  if (e == hipSuccess) e = launch_median_window(stack, T, (long long)N * N, sel, counts, psf, resid, st);
+  t.done();
+  return hip_ok(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, const float* stack,
+                                     const double* times, const double* parang_deg, double t_max,
+                                     double alpha_min_deg, float* psf_cube, float* resid, void* ws,
+                                     size_t ws_bytes, graphic_stream stream) {
+  int P = 0;
+  graphic_status s = window_args(ctx, geom, times, parang_deg, t_max, alpha_min_deg, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (!stack || (!psf_cube && !resid)) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t cube_b = (size_t)T * N * N * sizeof(float);
+  if (psf_cube && (overlap_bad(stack, psf_cube, cube_b) || psf_cube == stack)) return GRAPHIC_ERR_ARG;
+  if (resid && overlap_bad(stack, resid, cube_b)) return GRAPHIC_ERR_ARG;
+  if (psf_cube && resid && (overlap_bad(psf_cube, resid, cube_b) || psf_cube == resid)) return GRAPHIC_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, window_sel_bytes(T))) return GRAPHIC_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  return do_median_window(ctx, T, N, stack, times, parang_deg, t_max, alpha_min_deg, psf_cube, resid,
+                          static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
+                                         const double* dx, const double* dy, const double* parang_deg,
+                                         const double* times, double t_max, double alpha_min_deg,
+                                         float* final_img, float* psf_cube, float* residuals, void* ws,
+                                         size_t ws_bytes, graphic_stream stream) {
+  int P = 0;
+  graphic_status s = window_args(ctx, geom, times, parang_deg, t_max, alpha_min_deg, &P);
+  if (s != GRAPHIC_OK) return s;
+  if (!cube || !dx || !dy || !final_img) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t cube_b = (size_t)T * N * N * sizeof(float);
+  const size_t img_b = (size_t)N * N * sizeof(float);
+  auto inside = [&](const void* p, size_t b) {
+    const char* q = static_cast<const char*>(p);
+    const char* c = static_cast<const char*>(static_cast<const void*>(cube));
+    return q < c + cube_b && c < q + b;
+  };
+  if (inside(final_img, img_b)) return GRAPHIC_ERR_ARG;
+  if (psf_cube && (inside(psf_cube, cube_b) || overlap_bad(psf_cube, final_img, img_b))) return GRAPHIC_ERR_ARG;
+  if (residuals && (inside(residuals, cube_b) || overlap_bad(residuals, final_img, img_b))) return GRAPHIC_ERR_ARG;
+  if (psf_cube && residuals && overlap_bad(psf_cube, residuals, cube_b)) return GRAPHIC_ERR_ARG;
+  const size_t stack_b = residuals ? 0 : align_up(cube_b);
+  const size_t fixed = stack_b + window_sel_bytes(T);
+  const RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, 0);
+  if (!ws_ok(ws, ws_bytes, fixed + L.params + align_up((size_t)N * P * sizeof(float)))) return GRAPHIC_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  float* stack = residuals ? residuals : reinterpret_cast<float*>(w);
+  ShiftItem sh{cube, stack, T, dx, dy};
+  if ((s = do_shift_batch(ctx, N, P, &sh, 1, st)) != GRAPHIC_OK) return s;
+  if ((s = do_median_window(ctx, T, N, stack, times, parang_deg, t_max, alpha_min_deg, psf_cube, stack,
+                            w + stack_b, st)) != GRAPHIC_OK)
+    return s;
+  RotItem rot{stack, stack, T, parang_deg};
+  if ((s = do_rotate_batch(ctx, N, P, &rot, 1, -1.0, w + fixed, ws_bytes - fixed, st)) != GRAPHIC_OK) return s;
+  return do_median(ctx, T, N, stack, final_img, nullptr, st);
 }
 
 graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,

@@ -101,6 +101,15 @@ hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* lis
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
                          int variant, hipStream_t s);
 
+// Frame selection of the per-frame PSF (sel: [T][64] bit rows, counts: [T]).
+hipError_t launch_select_frames(const double* times, const double* parang, long long T, double t_max,
+                                double alpha_min, unsigned long long* sel, int* counts, hipStream_t s);
+
+// Per-frame medians over selected frames of a [T][npix] stack (T <= 2048):
+// psf[f] (nullable) and resid[f] = stack[f] - psf[f] (nullable, may be stack).
+hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
+                                const int* counts, float* psf, float* resid, hipStream_t s);
+
 // n floats of seeded noise around a sky level (for timing runs on scratch).
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
 

@@ -60,94 +60,138 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t frames_rsrc(const float* base,
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// Shared state of one block's select (one slot per pixel of the tile).
+template <int kPix>
+struct SelShared {
+  unsigned prefix[kPix], rank[kPix], cnt[kPix], min[kPix], lo[kPix];
+  float med[kPix];
+};
+
+// Geometry of a block's pixel tile and its frame groups.
+template <int kPix>
+struct Tile {
+  int tid, lane, wave, px, sub, g;
+  long long pix, pix0;
+  bool pix_ok;
+  unsigned voff, extent, extent_last;
+  int last, Ti;
+  unsigned long long gstride;
+
+  __device__ Tile(long long T, long long npix) {
+    constexpr int kSub = 64 / kPix;
+    tid = threadIdx.x;
+    lane = tid & 63;
+    wave = tid >> 6;
+    px = lane % kPix;
+    sub = lane / kPix;
+    g = sub + kSub * wave;                         // frame group 0..63
+    // The hardware deals consecutive block ids to the eight XCDs in turn; the
+    // remap gives each XCD a contiguous run of pixel tiles, so the two
+    // 64-byte halves of a 128-byte line are read by blocks that run side by
+    // side on one L2 (and each frame row is read in long runs).
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+    pix0 = (long long)tile * kPix;
+    pix = pix0 + px;
+    pix_ok = pix < npix;
+    // Frames 64 i .. 64 i + 63 form group i.  One wave-uniform buffer
+    // descriptor per group keeps the per-lane address a single 32-bit offset
+    // (g * npix + px) * 4: the base advances by 64 frames per group, full
+    // groups share one extent, and the last group's extent ends after frame
+    // T - 1, so lanes past it (and groups past T) read 0 and their stores are
+    // dropped.
+    Ti = (int)T;                                   // T <= 4096
+    voff = pix_ok ? (unsigned)(((long long)g * npix + px) * 4) : 0x80000000u;
+    extent = (unsigned)(((long long)(kGroups - 1) * npix + kPix) * 4);
+    last = (Ti - 1) / kGroups;
+    extent_last = (unsigned)((((long long)(Ti - 1) - (long long)kGroups * last) * npix + (npix - pix0)) * 4);
+    gstride = (unsigned long long)kGroups * (unsigned long long)npix * 4ull;
+  }
+  __device__ unsigned group_ext(int i) const { return i < last ? extent : (i == last ? extent_last : 0u); }
+};
+
+// Keys of frames g, g + 64, g + 128, ... of this thread's pixel; frames past
+// T get the largest key.
 template <int VPT, int kPix, bool BUF>
-__global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __restrict__ stack, long long T,
-                                                                long long npix, float* __restrict__ out,
-                                                                float* resid) {
-  constexpr int kThreads = kPix * kGroups;
-  constexpr int kSub = 64 / kPix;                  // lane groups of one pixel inside a wave
-  // one sub-histogram per (pixel, lane group), in dynamic LDS
-  extern __shared__ unsigned hist[];
-  __shared__ unsigned sel_prefix[kPix], sel_rank[kPix], sel_cnt[kPix], sel_min[kPix], sel_lo[kPix];
-  __shared__ float sel_med[kPix];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int px = lane % kPix;
-  const int sub = lane / kPix;
-  const int g = sub + kSub * wave;                 // frame group 0..63
-  // The hardware deals consecutive block ids to the eight XCDs in turn; the
-  // remap gives each XCD a contiguous run of pixel tiles, so the two 64-byte
-  // halves of a 128-byte line are read by blocks that run side by side on
-  // one L2 (and each frame row is read in long runs).
-  const unsigned nb = gridDim.x, b = blockIdx.x;
-  const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  const long long pix = (long long)tile * kPix + px;
-  const bool pix_ok = pix < npix;
-  unsigned* my_hist = hist + (px * kSub + sub) * kHistWords;
-
-  // Frames 64 i .. 64 i + 63 form group i.  One wave-uniform buffer
-  // descriptor per group keeps the per-lane address a single 32-bit offset
-  // (g * npix + px) * 4: the base advances by 64 frames per group, full groups
-  // share one extent, and the last group's extent ends after frame T - 1, so
-  // lanes past it (and groups past T) read 0 and their stores are dropped.
-  const int Ti = (int)T;                                   // T <= 4096
-  const long long pix0 = (long long)tile * kPix;
-  const unsigned voff = pix_ok ? (unsigned)(((long long)g * npix + (pix - pix0)) * 4) : 0x80000000u;
-  const unsigned extent = (unsigned)(((long long)(kGroups - 1) * npix + kPix) * 4);
-  const int last = (Ti - 1) / kGroups;
-  const unsigned extent_last =
-      (unsigned)((((long long)(Ti - 1) - (long long)kGroups * last) * npix + (npix - pix0)) * 4);
-  const unsigned long long gstride = (unsigned long long)kGroups * (unsigned long long)npix * 4ull;
-  auto group_ext = [&](int i) { return i < last ? extent : (i == last ? extent_last : 0u); };
-  unsigned key[VPT];
-  unsigned long long gaddr = reinterpret_cast<unsigned long long>(stack + pix0);   // group i's base, advanced per group
+__device__ __forceinline__ void load_keys(const Tile<kPix>& t, const float* __restrict__ stack, long long npix,
+                                          unsigned (&key)[VPT]) {
+  unsigned long long gaddr = reinterpret_cast<unsigned long long>(stack + t.pix0);   // group i's base
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
-    const bool valid = g + kGroups * i < Ti;
+    const bool valid = t.g + kGroups * i < t.Ti;
     float v;
     if constexpr (BUF) {
       v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-          frames_rsrc(reinterpret_cast<const float*>(gaddr), group_ext(i)), (int)voff, 0, 0));
-      gaddr += gstride;
+          frames_rsrc(reinterpret_cast<const float*>(gaddr), t.group_ext(i)), (int)t.voff, 0, 0));
+      gaddr += t.gstride;
     } else {
-      v = (valid && pix_ok) ? stack[(long long)(g + kGroups * i) * npix + pix] : 0.0f;   // frames too large for 32-bit offsets
+      v = (valid && t.pix_ok) ? stack[(long long)(t.g + kGroups * i) * npix + t.pix] : 0.0f;   // frames too large for 32-bit offsets
     }
     key[i] = valid ? key_of(v) : 0xFFFFFFFFu;   // padding sorts after every real (non-NaN) value
   }
+}
 
-  const unsigned k_lo = (unsigned)((T - 1) / 2);
-  if (tid < kPix) {
-    sel_prefix[tid] = 0u;
-    sel_rank[tid] = k_lo;
-    sel_lo[tid] = 0xFFFFFFFFu;
+// Writes value - med for every frame of this thread (in place is allowed:
+// each thread rewrites exactly the values it read).
+template <int VPT, int kPix, bool BUF>
+__device__ __forceinline__ void store_diff(const Tile<kPix>& t, float* resid, long long npix,
+                                           const unsigned (&key)[VPT], const float (&med)[VPT]) {
+  unsigned long long raddr = reinterpret_cast<unsigned long long>(resid + t.pix0);
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const float r = val_of(key[i]) - med[i];
+    if constexpr (BUF) {
+      __builtin_amdgcn_raw_buffer_store_b32(
+          __float_as_int(r), frames_rsrc(reinterpret_cast<const float*>(raddr), t.group_ext(i)), (int)t.voff, 0, 0);
+      raddr += t.gstride;
+    } else {
+      const int f = t.g + kGroups * i;
+      if (t.pix_ok && f < t.Ti) resid[(long long)f * npix + t.pix] = r;
+    }
   }
+}
 
+// Exact median of the keys whose bit is set in `bits` (bit i: key[i]); K is
+// how many keys of the pixel take part (K >= 1).  Every thread of the block
+// calls it; on return sh.med[px] holds the median of every pixel.
+template <int VPT, int kPix>
+__device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigned (&key)[VPT],
+                                              unsigned long long bits, unsigned K, unsigned* hist,
+                                              SelShared<kPix>& sh) {
+  constexpr int kThreads = kPix * kGroups;
+  constexpr int kSub = 64 / kPix;
+  unsigned* my_hist = hist + (t.px * kSub + t.sub) * kHistWords;
+  const unsigned k_lo = (K - 1) / 2;
+  if (t.tid < kPix) {
+    sh.prefix[t.tid] = 0u;
+    sh.rank[t.tid] = k_lo;
+    sh.lo[t.tid] = 0xFFFFFFFFu;
+  }
   unsigned mask = 0u;
   bool single = false;                              // every pixel's bin holds one key
 #pragma unroll 1
   for (int d = 3; d >= 0; --d) {
-    for (int i = tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
+    for (int i = t.tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
     __syncthreads();
-    const unsigned prefix = sel_prefix[px];
-    const int sh = 8 * d;
-    // (mask = 0 and prefix = 0 for the first digit: every key counts)
+    const unsigned prefix = sh.prefix[t.px];
+    const int shft = 8 * d;
+    // (mask = 0 and prefix = 0 for the first digit: every taking-part key counts)
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const unsigned bin = ((key[i] & mask) == prefix) ? ((key[i] >> sh) & 0xFFu) : (unsigned)kBins;
+      const bool in = ((bits >> i) & 1ull) != 0ull && (key[i] & mask) == prefix;
+      const unsigned bin = in ? ((key[i] >> shft) & 0xFFu) : (unsigned)kBins;
       atomicAdd(&my_hist[bin], 1u);
     }
     __syncthreads();
     // wave w scans the histogram of pixel w: lane l holds bins l, l+64, l+128, l+192
-    for (int w = wave; w < kPix; w += kThreads / 64) {
-      const unsigned k = sel_rank[w];
+    for (int w = t.wave; w < kPix; w += kThreads / 64) {
+      const unsigned k = sh.rank[w];
       unsigned carry = 0u;
       int found_bin = -1;
       unsigned below = 0u, inbin = 0u;
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk) {
-        const int bin = blk * 64 + lane;
+        const int bin = blk * 64 + t.lane;
         unsigned x = 0u;
 #pragma unroll
         for (int q = 0; q < kSub; ++q) x += hist[(w * kSub + q) * kHistWords + bin];
@@ -164,19 +208,19 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
         }
         carry += tot;
       }
-      if (lane == 0) {
-        sel_prefix[w] = sel_prefix[w] | ((unsigned)found_bin << sh);
-        sel_rank[w] = k - below;
-        sel_cnt[w] = inbin;
-        sel_min[w] = 0xFFFFFFFFu;
+      if (t.lane == 0) {
+        sh.prefix[w] = sh.prefix[w] | ((unsigned)found_bin << shft);
+        sh.rank[w] = k - below;
+        sh.cnt[w] = inbin;
+        sh.min[w] = 0xFFFFFFFFu;
       }
     }
-    mask |= 0xFFu << sh;
+    mask |= 0xFFu << shft;
     __syncthreads();
     if (d > 0) {
       unsigned most = 0u;
 #pragma unroll
-      for (int q = 0; q < kPix; ++q) most = max(most, sel_cnt[q]);
+      for (int q = 0; q < kPix; ++q) most = max(most, sh.cnt[q]);
       if (most <= 1u) {                             // block-uniform
         single = true;
         break;
@@ -185,54 +229,118 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   }
 
   // lo: the full key is the prefix after four digits; after an early stop it
-  // is the one key that carries the selected prefix.
+  // is the one taking-part key that carries the selected prefix.
   unsigned lo_key;
   if (single) {
-    const unsigned prefix = sel_prefix[px];
+    const unsigned prefix = sh.prefix[t.px];
 #pragma unroll
     for (int i = 0; i < VPT; ++i)
-      if ((key[i] & mask) == prefix) atomicMin(&sel_lo[px], key[i]);
+      if (((bits >> i) & 1ull) != 0ull && (key[i] & mask) == prefix) atomicMin(&sh.lo[t.px], key[i]);
     __syncthreads();
-    lo_key = sel_lo[px];
+    lo_key = sh.lo[t.px];
   } else {
-    lo_key = sel_prefix[px];
+    lo_key = sh.prefix[t.px];
   }
-  // sel_rank is lo's rank among the keys that carry its prefix and sel_cnt
-  // how many keys carry it (after four digits: how many equal lo); rank T/2
-  // still hits lo iff it falls inside that run, otherwise hi is the smallest
-  // key above lo.
+  // sh.rank is lo's rank among the keys that carry its prefix and sh.cnt how
+  // many keys carry it (after four digits: how many equal lo); rank K/2 still
+  // hits lo iff it falls inside that run, otherwise hi is the smallest
+  // taking-part key above lo.
   unsigned local_min = 0xFFFFFFFFu;
 #pragma unroll
   for (int i = 0; i < VPT; ++i)
-    if (key[i] > lo_key && key[i] < local_min) local_min = key[i];
-  atomicMin(&sel_min[px], local_min);
+    if (((bits >> i) & 1ull) != 0ull && key[i] > lo_key && key[i] < local_min) local_min = key[i];
+  atomicMin(&sh.min[t.px], local_min);
   __syncthreads();
-
-  if (g == 0) {
-    const unsigned step = (unsigned)(T / 2) - k_lo;      // 0 (odd T) or 1
+  if (t.g == 0) {
+    const unsigned step = K / 2 - k_lo;                  // 0 (odd K) or 1
     const float lo = val_of(lo_key);
-    const float hi = (sel_rank[px] + step < sel_cnt[px]) ? lo : val_of(sel_min[px]);
-    const float med = (lo + hi) * 0.5f;
-    sel_med[px] = med;
-    if (pix_ok) out[pix] = med;
+    const float hi = (sh.rank[t.px] + step < sh.cnt[t.px]) ? lo : val_of(sh.min[t.px]);
+    sh.med[t.px] = (lo + hi) * 0.5f;
   }
+  __syncthreads();
+}
+
+template <int VPT, int kPix, bool BUF>
+__global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __restrict__ stack, long long T,
+                                                                long long npix, float* __restrict__ out,
+                                                                float* resid) {
+  extern __shared__ unsigned hist[];     // one sub-histogram per (pixel, lane group)
+  __shared__ SelShared<kPix> sh;
+  const Tile<kPix> t(T, npix);
+  unsigned key[VPT];
+  load_keys<VPT, kPix, BUF>(t, stack, npix, key);
+  select_median<VPT, kPix>(t, key, ~0ull, (unsigned)T, hist, sh);
+  const float med = sh.med[t.px];
+  if (t.g == 0 && t.pix_ok) out[t.pix] = med;
   if (resid != nullptr) {
-    __syncthreads();
-    const float med = sel_med[px];
-    unsigned long long raddr = reinterpret_cast<unsigned long long>(resid + pix0);
+    float m[VPT];
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-      const float r = val_of(key[i]) - med;
-      if constexpr (BUF) {
-        __builtin_amdgcn_raw_buffer_store_b32(
-            __float_as_int(r), frames_rsrc(reinterpret_cast<const float*>(raddr), group_ext(i)), (int)voff, 0, 0);
-        raddr += gstride;
-      } else {
-        const int t = g + kGroups * i;
-        if (pix_ok && t < Ti) resid[(long long)t * npix + pix] = r;
-      }
+    for (int i = 0; i < VPT; ++i) m[i] = med;
+    store_diff<VPT, kPix, BUF>(t, resid, npix, key, m);
+  }
+}
+
+// Per-frame medians over selected frames: for every frame f, the median of
+// the frames whose bit is set in row f of the selection (sel[f][g] bit i:
+// frame g + 64 i), written to psf[f] (nullable) and subtracted from frame f
+// into resid (nullable; in place allowed).  One block keeps its pixel tile's
+// whole stack in registers and runs the select once per frame.
+template <int VPT, bool BUF>
+__global__ void __launch_bounds__(16 * kGroups)
+median_window_kernel(const float* __restrict__ stack, long long T, long long npix,
+                     const unsigned long long* __restrict__ sel, const int* __restrict__ counts,
+                     float* __restrict__ psf, float* resid) {
+  constexpr int kPix = 16;
+  extern __shared__ unsigned hist[];
+  __shared__ SelShared<kPix> sh;
+  const Tile<kPix> t(T, npix);
+  unsigned key[VPT];
+  load_keys<VPT, kPix, BUF>(t, stack, npix, key);
+  float med_own[VPT];                                    // median of each of this thread's frames
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) med_own[i] = 0.0f;
+#pragma unroll 1
+  for (int f = 0; f < t.Ti; ++f) {
+    const unsigned long long bits = sel[(size_t)f * kGroups + t.g];
+    select_median<VPT, kPix>(t, key, bits, (unsigned)counts[f], hist, sh);
+    const float m = sh.med[t.px];
+    if (t.g == 0 && t.pix_ok && psf != nullptr) psf[(size_t)f * npix + t.pix] = m;
+    if (t.g == (f & (kGroups - 1))) {
+#pragma unroll
+      for (int i = 0; i < VPT; ++i)
+        if (i == (f >> 6)) med_own[i] = m;
     }
   }
+  if (resid != nullptr) store_diff<VPT, kPix, BUF>(t, resid, npix, key, med_own);
+}
+
+// Frame selection of the per-frame PSF: row f marks the frames k with
+// |t_k - t_f| < t_max and |alpha_k - alpha_f| > alpha_min, packed as
+// sel[f][g] bit i = frame g + 64 i; a row with no frame falls back to every
+// frame.  counts[f] = frames in row f.  One block of 64 threads per row.
+__global__ void __launch_bounds__(64) select_frames_kernel(const double* __restrict__ times,
+                                                           const double* __restrict__ parang, long long T,
+                                                           double t_max, double alpha_min,
+                                                           unsigned long long* __restrict__ sel,
+                                                           int* __restrict__ counts) {
+  const long long f = blockIdx.x;
+  const int g = threadIdx.x;
+  const double tf = times[f], af = parang[f];
+  unsigned long long bits = 0ull, all = 0ull;
+  for (int i = 0; i < 64; ++i) {
+    const long long k = g + 64LL * i;
+    if (k >= T) break;
+    all |= 1ull << i;
+    if (fabs(times[k] - tf) < t_max && fabs(parang[k] - af) > alpha_min) bits |= 1ull << i;
+  }
+  int c = __popcll(bits);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (c == 0) {
+    bits = all;
+    c = (int)T;
+  }
+  sel[f * 64 + g] = bits;
+  if (g == 0) counts[f] = c;
 }
 
 }  // namespace
@@ -269,6 +377,46 @@ static hipError_t launch_median_pix(const float* stack, long long T, long long n
   GRAPHIC_MEDIAN_CASE(64)
 #undef GRAPHIC_MEDIAN_CASE
   return hipErrorInvalidValue;   // T > 4096: rejected on the host before launch
+}
+
+hipError_t launch_select_frames(const double* times, const double* parang, long long T, double t_max,
+                                double alpha_min, unsigned long long* sel, int* counts, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(select_frames_kernel, dim3((unsigned)T), dim3(64), 0, s, times, parang, T, t_max, alpha_min,
+                     sel, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
+                                const int* counts, float* psf, float* resid, hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  const long long vpt = (T + kGroups - 1) / kGroups;
+  const unsigned blocks = (unsigned)((npix + 15) / 16);
+  const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
+  const size_t lds = (size_t)16 * 4 * kHistWords * sizeof(unsigned);
+#define GRAPHIC_WINDOW_CASE(V)                                                                             \
+  if (vpt <= V) {                                                                                         \
+    if (buf) {                                                                                            \
+      hipFuncSetAttribute((const void*)median_window_kernel<V, true>,                                     \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                          \
+      hipLaunchKernelGGL((median_window_kernel<V, true>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, \
+                         T, npix, sel, counts, psf, resid);                                               \
+    } else {                                                                                              \
+      hipFuncSetAttribute((const void*)median_window_kernel<V, false>,                                    \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                          \
+      hipLaunchKernelGGL((median_window_kernel<V, false>), dim3(blocks), dim3(16 * kGroups), lds, s,      \
+                         stack, T, npix, sel, counts, psf, resid);                                        \
+    }                                                                                                     \
+    return hipGetLastError();                                                                             \
+  }
+  GRAPHIC_WINDOW_CASE(1)
+  GRAPHIC_WINDOW_CASE(2)
+  GRAPHIC_WINDOW_CASE(4)
+  GRAPHIC_WINDOW_CASE(8)
+  GRAPHIC_WINDOW_CASE(16)
+  GRAPHIC_WINDOW_CASE(32)
+#undef GRAPHIC_WINDOW_CASE
+  return hipErrorInvalidValue;   // T > 2048: rejected on the host before launch
 }
 
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid, int variant,

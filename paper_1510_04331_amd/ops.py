@@ -159,6 +159,66 @@ def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, w
     return out[0] if len(out) == 1 else tuple(out)
 
 
+def alpha_min_deg(n_fwhm, fwhm, r_min):
+    """Minimum field rotation (degrees) of the per-frame PSF selection: the
+    chord angle 2 arcsin(n_fwhm * fwhm / (2 r_min)) at which a point at radius
+    r_min has moved by n_fwhm FWHM."""
+    import math
+    x = n_fwhm * fwhm / (2.0 * r_min)
+    if not 0.0 <= x <= 1.0:
+        raise ValueError("n_fwhm * fwhm must lie in [0, 2 r_min]")
+    return math.degrees(2.0 * math.asin(x))
+
+
+def median_window(stack, times, parang_deg, t_max, alpha_min, psf=True, resid=False, inplace=False):
+    """Per-frame medians over the frames selected for each frame (time
+    separation below t_max, rotation above alpha_min degrees).  Returns the
+    PSF cube and/or the residual cube stack - PSF (written into ``stack``
+    when ``inplace``)."""
+    import torch
+    T, N = _check_cube(stack, "stack")
+    dev = stack.device
+    t = _f64(times, T, dev, "times")
+    pa = _f64(parang_deg, T, dev, "parang_deg")
+    psf_t = torch.empty_like(stack) if psf else None
+    res_t = stack if inplace else (torch.empty_like(stack) if resid else None)
+    ws, n = _workspace(_abi.OP_MEDIAN_WINDOW, T, N, None, dev)
+    g = _geom(T, N, None)
+    _abi.check(_abi.load().graphic_median_window(context(dev.index or 0), ctypes.byref(g), _ptr(stack), _ptr(t),
+                                                 _ptr(pa), float(t_max), float(alpha_min), _ptr(psf_t),
+                                                 _ptr(res_t), _ptr(ws), n, _stream(dev)), "graphic_median_window")
+    out = [x for x in (psf_t, res_t) if x is not None]
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def adi_reduce_window(cube, dx, dy, parang_deg, times, t_max, alpha_min, pad=None, psf=False, residuals=False,
+                      workspace=None, stream=None):
+    """ADI with the per-frame PSF of the paper's frame selection.  Returns the
+    final image, plus the PSF cube and the derotated residual cube when
+    asked."""
+    import torch
+    T, N = _check_cube(cube)
+    dev = cube.device
+    dx, dy = _f64(dx, T, dev, "dx"), _f64(dy, T, dev, "dy")
+    pa = _f64(parang_deg, T, dev, "parang_deg")
+    t = _f64(times, T, dev, "times")
+    final = torch.empty((N, N), dtype=torch.float32, device=dev)
+    psf_t = torch.empty_like(cube) if psf else None
+    res_t = torch.empty_like(cube) if residuals else None
+    if workspace is None:
+        ws, n = _workspace(_abi.OP_ADI_WINDOW, T, N, pad, dev)
+    else:
+        ws, n = workspace, workspace.numel()
+    g = _geom(T, N, pad)
+    st = _on_stream(stream, dev, [cube, dx, dy, pa, t, final, psf_t, res_t, ws])
+    _abi.check(_abi.load().graphic_adi_reduce_window(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(dx),
+                                                     _ptr(dy), _ptr(pa), _ptr(t), float(t_max), float(alpha_min),
+                                                     _ptr(final), _ptr(psf_t), _ptr(res_t), _ptr(ws), n, st),
+               "graphic_adi_reduce_window")
+    out = [final] + [x for x in (psf_t, res_t) if x is not None]
+    return out[0] if len(out) == 1 else tuple(out)
+
+
 def _batch_descs(cubes, dx, dy, parang, pad, psf, residuals):
     import torch
     n = len(cubes)

@@ -73,3 +73,22 @@ def test_entry_points_reject_null_context(lib):
     assert lib.graphic_adi_reduce(None, ctypes.byref(g), None, None, None, None, None, None, None, None, 0,
                                   None) == _abi.ERR_ARG
     assert lib.graphic_median(None, ctypes.byref(g), None, None, None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_median_window(None, ctypes.byref(g), None, None, None, 1.0, 1.0, None, None, None, 0,
+                                     None) == _abi.ERR_ARG
+    assert lib.graphic_adi_reduce_window(None, ctypes.byref(g), None, None, None, None, None, 1.0, 1.0, None, None,
+                                         None, None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_autotune(None, ctypes.byref(g), None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_tuning_import(None, b"") == _abi.ERR_ARG
+    assert lib.graphic_graph_launch(None, None) == _abi.ERR_ARG
+
+
+def test_window_workspace_sizes(lib):
+    sz = ctypes.c_size_t()
+    g = _abi.Geom(100, 64, 0, 0)
+    assert lib.graphic_workspace_size(None, _abi.OP_MEDIAN_WINDOW, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 100 * 64 * 8 + 100 * 4
+    assert lib.graphic_workspace_size(None, _abi.OP_ADI_WINDOW, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 100 * 64 * 64 * 4 + 100 * 64 * 8 + 64 * 128 * 4
+    big = _abi.Geom(2049, 64, 0, 0)       # the per-frame PSF holds up to 2048 frames
+    for op in (_abi.OP_MEDIAN_WINDOW, _abi.OP_ADI_WINDOW):
+        assert lib.graphic_workspace_size(None, op, ctypes.byref(big), ctypes.byref(sz)) == _abi.ERR_UNSUPPORTED
