@@ -5,4 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 """
 
 from .fourier_adi import *  # noqa: F401,F403
-from .fourier_adi import __all__  # noqa: F401
+from .fourier_adi import __all__ as _adi_all
+from . import registration  # noqa: F401  (Sect. 2: parallactic angles, centroid, Moffat fit)
+
+__all__ = list(_adi_all) + ["registration"]
