@@ -18,6 +18,8 @@ Two more workloads print their own JSON line:
         streams), against one request at a time
     python bench.py --workload window   ADI with the per-frame PSF of the
         paper's frame selection, 1024 frames of 512^2
+    python bench.py --workload register registration (centroid + Moffat fit)
+        of 1024 frames of 512^2
 """
 
 import argparse
@@ -302,6 +304,34 @@ def bench_window(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_register(args):
+    """Registration of the NACO-like cube (1024 frames of 512^2): brightest
+    pixel over the whole frame, patch centroid, Moffat fit over 24 x 24."""
+    import torch
+    import paper_1510_04331_amd as G
+    import synth
+    dev = torch.device("cuda:0")
+    p = synth.make_params(2)
+    cube = synth.render_device(p, dev)
+    for _ in range(args.warmup):
+        G.register(cube, 500.0, 4, 5000, half=12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = G.register(cube, 500.0, 4, 5000, half=12)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    flags = res["flags"].cpu()
+    err = float(max((res["dx"].cpu().numpy() - p.dx).__abs__().max(), (res["dy"].cpu().numpy() - p.dy).__abs__().max()))
+    out = {"metric": "frames registered/s (centroid + Moffat fit)", "value": round(p.T / dt, 1), "unit": "frames/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt, 3),
+           "higher_is_better": True, "dtype": "f64 fit on f32 frames", "data": "synthetic",
+           "config": {"workload": "NACO-like cube, 1024 frames of 512x512, threshold 500, fit box 24x24"},
+           "centroid_found": int((flags & 1).sum()), "fit_converged": int(((flags >> 1) & 1).sum()),
+           "max_shift_error_px": round(err, 4)}
+    print(json.dumps(out), flush=True)
+
+
 def bench_served(args):
     import numpy as np
     import torch
@@ -365,7 +395,7 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("adi", "batch", "served", "window"), default="adi")
+    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register"), default="adi")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning (default launch shapes; keeps tuning launches out of profiles)")
     ap.add_argument("--requests", type=int, default=1000)
@@ -390,6 +420,8 @@ def main():
         return bench_served(args)
     if args.workload == "window":
         return bench_window(args)
+    if args.workload == "register":
+        return bench_register(args)
 
     cpu = None
     if not args.no_cpu_baseline:

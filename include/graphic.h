@@ -210,6 +210,48 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
                                          void* ws, size_t ws_bytes, graphic_stream stream);
 
 /*
+ * Registration (Sect. 2).
+ *
+ * graphic_parallactic_angles: per-frame parallactic angle in degrees from the
+ * local sidereal time (seconds), with hour angle h = 15 LST / 3600 - ra_deg:
+ *   atan2(cos(lat) sin(h), cos(dec) sin(lat) - sin(dec) cos(lat) cos(h))
+ * (the two-argument arctangent fixes the quadrant).  lst_s, out: [T] float64.
+ *
+ * graphic_register: per frame (one block each), the star centroid and a
+ * Moffat fit (Sect. 2.2).  The centroid is the centre of mass, weighted by
+ * pixel values, of the 4-connected patch of pixels above `threshold` that
+ * holds the brightest pixel, grown inside a 64 x 64 box around it; a patch
+ * whose size lies outside [min_size, max_size] fails and the brightest pixel
+ * stands in.  The fit is least squares of
+ *   I0 (beta - 1) / (pi alpha^2) (1 + ((x-x0)^2 + (y-y0)^2) / alpha^2)^-beta + Bg
+ * over the (2 half)^2 box around the rounded centroid (clipped to the frame),
+ * pixels at or above `saturation` and non-finite pixels masked, by
+ * Levenberg-Marquardt in float64 from: Bg = mean of the unmasked box-border
+ * pixels, alpha = beta = 2.5, (x0, y0) = centroid, I0 matching the brightest
+ * unmasked pixel.  Pixel (x, y) is column x, row y; the recentring shift of
+ * graphic_shift is (N/2 - x0, N/2 - y0).  FWHM = 2 alpha sqrt(2^(1/beta) - 1).
+ *   cube  : [T][N][N] float32.
+ *   out   : [T][9] float64: centroid x, y; x0, y0, I0, alpha, beta, Bg; the
+ *           final half sum of squared residuals.
+ *   flags : [T] int32: bit 0 centroid patch found, bit 1 fit converged.
+ * Errors: GRAPHIC_ERR_ARG for null pointers, half outside 1..32, min_size >
+ * max_size or max_iter < 1; geometry errors as graphic_shift.
+ */
+typedef struct {
+    double threshold;            /* patch threshold (frame units) */
+    int32_t min_size, max_size;  /* accepted patch sizes in pixels */
+    int32_t half;                /* fit box half side, 1..32 */
+    int32_t max_iter;            /* Levenberg-Marquardt iterations, >= 1 */
+    double saturation;           /* mask level (use +inf for none) */
+} graphic_register_params;
+
+graphic_status graphic_parallactic_angles(graphic_ctx ctx, const double* lst_s, int64_t n_frames, double ra_deg,
+                                          double dec_deg, double lat_deg, double* out_deg, graphic_stream stream);
+graphic_status graphic_register(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
+                                const graphic_register_params* params, double* out, int32_t* flags,
+                                graphic_stream stream);
+
+/*
  * Batched ADI reduction of cubes of uneven frame count and size (the
  * classical reduction of graphic_adi_reduce applied to every cube).  Cubes
  * with the same N and P form a size class; every line pass of a class runs

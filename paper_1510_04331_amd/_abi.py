@@ -19,6 +19,7 @@ EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
     "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_adi_reduce_window",
+    "graphic_parallactic_angles", "graphic_register",
     "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
     "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
     "graphic_autotune", "graphic_tuning_export", "graphic_tuning_import",
@@ -37,6 +38,11 @@ class CubeDesc(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p),
                 ("parang_deg", ctypes.c_void_p), ("final_img", ctypes.c_void_p), ("psf", ctypes.c_void_p),
                 ("residuals", ctypes.c_void_p)]
+
+
+class RegisterParams(ctypes.Structure):
+    _fields_ = [("threshold", ctypes.c_double), ("min_size", ctypes.c_int32), ("max_size", ctypes.c_int32),
+                ("half", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("saturation", ctypes.c_double)]
 
 
 class GraphicError(RuntimeError):
@@ -85,6 +91,10 @@ def load():
     lib.graphic_median_window.restype = st
     lib.graphic_adi_reduce_window.argtypes = [vp, g, vp, vp, vp, vp, vp, f64, f64, vp, vp, vp, vp, sz, vp]
     lib.graphic_adi_reduce_window.restype = st
+    lib.graphic_parallactic_angles.argtypes = [vp, vp, i64, f64, f64, f64, vp, vp]
+    lib.graphic_parallactic_angles.restype = st
+    lib.graphic_register.argtypes = [vp, g, vp, ctypes.POINTER(RegisterParams), vp, vp, vp]
+    lib.graphic_register.restype = st
     cd = ctypes.POINTER(CubeDesc)
     lib.graphic_batch_workspace_size.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)]
     lib.graphic_batch_workspace_size.restype = st

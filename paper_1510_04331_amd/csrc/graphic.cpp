@@ -813,6 +813,39 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
   return do_median(ctx, T, N, stack, final_img, nullptr, st);
 }
 
+graphic_status graphic_parallactic_angles(graphic_ctx ctx, const double* lst_s, int64_t n_frames, double ra_deg,
+                                          double dec_deg, double lat_deg, double* out_deg, graphic_stream stream) {
+  if (!ctx || !lst_s || !out_deg || n_frames < 1) return GRAPHIC_ERR_ARG;
+  if (!std::isfinite(ra_deg) || !std::isfinite(dec_deg) || !std::isfinite(lat_deg)) return GRAPHIC_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Timer t(ctx, st, "aux");
+  hipError_t e = launch_parallactic(lst_s, n_frames, ra_deg, dec_deg, lat_deg, out_deg, st);
+  t.done();
+  return hip_ok(e);
+}
+
+graphic_status graphic_register(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
+                                const graphic_register_params* params, double* out, int32_t* flags,
+                                graphic_stream stream) {
+  if (!ctx || !geom || !cube || !params || !out || !flags) return GRAPHIC_ERR_ARG;
+  int P = 0;
+  graphic_status s = check_geom(geom, &P);
+  if (s != GRAPHIC_OK) return s;
+  const graphic_register_params& q = *params;
+  if (q.half < 1 || q.half > 32 || q.min_size > q.max_size || q.max_iter < 1 || std::isnan(q.threshold) ||
+      std::isnan(q.saturation))
+    return GRAPHIC_ERR_ARG;
+  if (geom->n_frames > 0x7fffffffLL) return GRAPHIC_ERR_UNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  RegisterParams prm{q.threshold, q.min_size, q.max_size, q.half, q.saturation, q.max_iter};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Timer t(ctx, st, "register");
+  hipError_t e = launch_register(cube, geom->n_frames, geom->n, prm, out, flags, st);
+  t.done();
+  return hip_ok(e);
+}
+
 graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,
                                             uint32_t flags, size_t* bytes) {
   if (!bytes) return GRAPHIC_ERR_ARG;

@@ -110,6 +110,22 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
                                 const int* counts, float* psf, float* resid, hipStream_t s);
 
+// Registration (Sect. 2).  Per frame, out[f * kRegisterOut + k]: centroid x,
+// y, fitted x0, y0, I0, alpha, beta, Bg, final half sum of squared
+// residuals; flags[f]: bit 0 centroid patch found, bit 1 fit converged.
+struct RegisterParams {
+  double threshold;      // patch threshold
+  int min_size, max_size;  // accepted patch sizes (pixels)
+  int half;              // fit box half side (1..32)
+  double saturation;     // pixels at or above it are masked in the fit
+  int max_iter;          // Levenberg-Marquardt iterations
+};
+constexpr int kRegisterOut = 9;
+hipError_t launch_register(const float* cube, long long T, int n, const RegisterParams& prm, double* out,
+                           int* flags, hipStream_t s);
+hipError_t launch_parallactic(const double* lst_s, long long T, double ra_deg, double dec_deg, double lat_deg,
+                              double* out, hipStream_t s);
+
 // n floats of seeded noise around a sky level (for timing runs on scratch).
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
 

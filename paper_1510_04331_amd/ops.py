@@ -219,6 +219,43 @@ def adi_reduce_window(cube, dx, dy, parang_deg, times, t_max, alpha_min, pad=Non
     return out[0] if len(out) == 1 else tuple(out)
 
 
+def parallactic_angles(lst_s, ra_deg, dec_deg, lat_deg, device=None):
+    """Per-frame parallactic angles (degrees) from local sidereal times in
+    seconds (a float64 tensor or array)."""
+    import torch
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    lst = torch.as_tensor(lst_s, dtype=torch.float64, device=dev).contiguous().reshape(-1)
+    out = torch.empty_like(lst)
+    _abi.check(_abi.load().graphic_parallactic_angles(context(dev.index or 0), _ptr(lst), lst.numel(), float(ra_deg),
+                                                      float(dec_deg), float(lat_deg), _ptr(out), _stream(dev)),
+               "graphic_parallactic_angles")
+    return out
+
+
+REGISTER_COLUMNS = ("cx", "cy", "x0", "y0", "i0", "alpha", "beta", "bg", "cost")
+
+
+def register(cube, threshold, min_size, max_size, half=16, saturation=float("inf"), max_iter=200):
+    """Star centroid and Moffat fit of every frame.  Returns a dict of float64
+    [T] tensors (REGISTER_COLUMNS plus fwhm, dx, dy) and int32 flags."""
+    import torch
+    T, N = _check_cube(cube)
+    dev = cube.device
+    out = torch.empty((T, 9), dtype=torch.float64, device=dev)
+    flags = torch.empty(T, dtype=torch.int32, device=dev)
+    prm = _abi.RegisterParams(float(threshold), int(min_size), int(max_size), int(half), int(max_iter),
+                              float(saturation))
+    g = _geom(T, N, None)
+    _abi.check(_abi.load().graphic_register(context(dev.index or 0), ctypes.byref(g), _ptr(cube), ctypes.byref(prm),
+                                            _ptr(out), _ptr(flags), _stream(dev)), "graphic_register")
+    res = {k: out[:, i] for i, k in enumerate(REGISTER_COLUMNS)}
+    res["fwhm"] = 2.0 * res["alpha"] * torch.sqrt(torch.pow(2.0, 1.0 / res["beta"]) - 1.0)
+    res["dx"] = N / 2.0 - res["x0"]
+    res["dy"] = N / 2.0 - res["y0"]
+    res["flags"] = flags
+    return res
+
+
 def _batch_descs(cubes, dx, dy, parang, pad, psf, residuals):
     import torch
     n = len(cubes)

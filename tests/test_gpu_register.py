@@ -1,0 +1,115 @@
+"""GPU: registration (Sect. 2) against the oracle.
+
+Parallactic angles agree to rounding (different math libraries).  The
+centroid is the same weighted mean of the same pixels (float64 sums in another
+order).  The Moffat fit minimises the same sum of squares over the same
+pixels from the same starting point with another Levenberg-Marquardt variant
+(analytic derivatives here, MINPACK's forward differences in the oracle), so
+both land on the same minimum: centres within 1e-6 px, other parameters
+within 1e-6 relative, and noiseless frames recover their true parameters.
+The stars are Moffat profiles, for which the least-squares minimum is
+finite."""
+
+import numpy as np
+import pytest
+
+from oracle import registration as R
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+def test_parallactic_angles(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    rng = np.random.default_rng(4)
+    lst = rng.uniform(0, 86400, 500)
+    for ra, dec, lat in ((83.6, -5.4, -24.6), (10.0, 60.0, 19.8), (300.0, -89.0, -24.6)):
+        got = G.parallactic_angles(lst, ra, dec, lat, device=dev).cpu().numpy()
+        ref = R.parallactic_angle(lst, ra, dec, lat)
+        d = np.abs((got - ref + 180.0) % 360.0 - 180.0)
+        assert d.max() < 1e-9
+
+
+def _check(got, ref, i):
+    assert abs(got["cx"][i] - ref["cx"][i]) < 1e-9 and abs(got["cy"][i] - ref["cy"][i]) < 1e-9, i
+    assert abs(got["x0"][i] - ref["x0"][i]) < 1e-6 and abs(got["y0"][i] - ref["y0"][i]) < 1e-6, i
+    for k in ("i0", "alpha", "beta"):
+        assert abs(got[k][i] - ref[k][i]) <= 1e-6 * abs(ref[k][i]), (i, k, got[k][i], ref[k][i])
+    assert abs(got["bg"][i] - ref["bg"][i]) <= 1e-6 * max(1.0, abs(ref["bg"][i])), i
+
+
+def _host(res):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+@pytest.mark.parametrize("sat", [float("inf"), 900.0])
+def test_register_noiseless_moffat(torch_dev, sat):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    n = 96
+    truth = [np.array([3e4, 47.3, 49.9, 2.4, 2.6, 15.0]), np.array([1.2e4, 44.0, 51.5, 3.1, 3.7, -4.0]),
+             np.array([8e3, 60.2, 33.3, 2.0, 2.2, 0.0])]
+    yy, xx = np.mgrid[0:n, 0:n]
+    cube = np.stack([np.minimum(R.moffat(p, xx, yy), sat) for p in truth]).astype(np.float32)
+    got = _host(G.register(torch.from_numpy(cube).to(dev), 40.0, 4, 3000, half=16, saturation=sat))
+    ref = R.register(cube, 40.0, 4, 3000, half=16, saturation=sat)
+    for i, p in enumerate(truth):
+        _check(got, ref, i)
+        assert int(got["flags"][i]) == 3
+        # float32 data: the true parameters to about the data's rounding
+        assert abs(got["x0"][i] - p[1]) < 1e-3 and abs(got["y0"][i] - p[2]) < 1e-3
+        assert abs(got["alpha"][i] - p[3]) < 1e-3 * p[3] and abs(got["beta"][i] - p[4]) < 1e-3 * p[4]
+
+
+def _noisy_moffat_cube(T, n, seed):
+    """Frames of a Moffat star (random sub-pixel offsets, seeing and wing
+    parameters) on a sky background, Poisson and read noise.  A Moffat star
+    gives the fit a finite minimum; a Gaussian core would not (the Moffat
+    family reaches the Gaussian only as alpha and beta grow without bound)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:n, 0:n]
+    truth = np.stack([rng.uniform(1e5, 4e5, T), n / 2 + rng.uniform(-1, 1, T), n / 2 + rng.uniform(-1, 1, T),
+                      rng.uniform(2.2, 2.8, T), rng.uniform(2.4, 3.2, T), np.full(T, 20.0)], axis=1)
+    cube = np.stack([rng.poisson(np.maximum(R.moffat(q, xx, yy), 0.0)) + rng.normal(0.0, 5.0, (n, n))
+                     for q in truth]).astype(np.float32)
+    return cube, truth
+
+
+def test_register_sky_frames(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("register noisy frames", flush=True)
+    n, T = 128, 12
+    cube, truth = _noisy_moffat_cube(T, n, 91)
+    cube[3, 10:14, 20:22] = np.nan                       # bad pixels, far from the star
+    i5 = int(truth[5, 2]) + 3, int(truth[5, 1]) - 2
+    cube[5, i5[0], i5[1]] = np.nan                       # one inside the fit box
+    got = _host(G.register(torch.from_numpy(cube).to(dev), 500.0, 4, 2000, half=12))
+    ref = R.register(cube, 500.0, 4, 2000, half=12)
+    for i in range(T):
+        _check(got, ref, i)
+        assert int(got["flags"][i]) == 3 and ref["centroid_ok"][i]
+    # the fitted centres find the injected ones to the noise level
+    assert np.abs(got["x0"] - truth[:, 1]).max() < 0.05 and np.abs(got["y0"] - truth[:, 2]).max() < 0.05
+
+
+def test_register_patch_rules(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    n = 64
+    yy, xx = np.mgrid[0:n, 0:n]
+    star = R.moffat(np.array([2e4, 30.0, 33.0, 2.5, 2.5, 1.0]), xx, yy)
+    cube = np.stack([star, star, star]).astype(np.float32)
+    for max_size, thr, ok in ((5, 50.0, False), (3000, 50.0, True), (3000, 1e9, False)):
+        got = _host(G.register(torch.from_numpy(cube).to(dev), thr, 4, max_size))
+        ref = R.register(cube, thr, 4, max_size)
+        assert all(bool(int(f) & 1) == ok for f in got["flags"])
+        assert np.array_equal(got["cx"], ref["cx"]) or np.allclose(got["cx"], ref["cx"], atol=1e-9)
