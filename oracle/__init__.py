@@ -7,5 +7,6 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 from .fourier_adi import *  # noqa: F401,F403
 from .fourier_adi import __all__ as _adi_all
 from . import registration  # noqa: F401  (Sect. 2: parallactic angles, centroid, Moffat fit)
+from . import preprocess  # noqa: F401  (Sect. 3.1-3.2: master sky, bad pixels)
 
-__all__ = list(_adi_all) + ["registration"]
+__all__ = list(_adi_all) + ["registration", "preprocess"]
