@@ -80,7 +80,9 @@ enum {
     GRAPHIC_OP_ADI = 2,
     GRAPHIC_OP_MEDIAN = 3,
     GRAPHIC_OP_MEDIAN_WINDOW = 4,
-    GRAPHIC_OP_ADI_WINDOW = 5
+    GRAPHIC_OP_ADI_WINDOW = 5,
+    GRAPHIC_OP_BADPIX_MAP = 6,
+    GRAPHIC_OP_BADPIX_FIX = 7
 };
 
 /* Geometry of one cube. */
@@ -250,6 +252,45 @@ graphic_status graphic_parallactic_angles(graphic_ctx ctx, const double* lst_s, 
 graphic_status graphic_register(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
                                 const graphic_register_params* params, double* out, int32_t* flags,
                                 graphic_stream stream);
+
+/*
+ * Image pre-processing (Sect. 3.1-3.2).  Frames as graphic_geom (T <= 65535).
+ *
+ * graphic_median_nan: per-pixel median of a stack ignoring NaN values, as
+ *   graphic_median over the values left (the master sky of Sect. 3.1 after
+ *   the star is masked); a pixel with no value left is NaN.  T <= 4096.
+ * graphic_mask_disk: sets to NaN, in place, the pixels of frame i with
+ *   (x - xs[i])^2 + (y - ys[i])^2 <= radius^2 (x column, y row; xs, ys [T]
+ *   float64).
+ * graphic_subtract_nearest: frame_i -= skies[s] in place, s the sky whose
+ *   time is closest to times[i] (the earliest on a tie); skies [S][N][N]
+ *   float32, sky_times [S] float64, times [T] float64, S >= 1.
+ * graphic_badpix_map: bad pixels of one N x N frame (a master dark or sky):
+ *   non-finite, or differing from the median of the finite pixels by more
+ *   than c_sigma times their standard deviation (float64).  map [N][N] uint8
+ *   (1 = bad); stats NULL or [3] float64 (median, mean, sigma).
+ *   ws: graphic_workspace_size(GRAPHIC_OP_BADPIX_MAP) bytes (geometry T = 1).
+ * graphic_badpix_fix: sets the pixels of `map` (NULL: none) to NaN in every
+ *   frame, then fills, pass after pass, every NaN pixel that has non-NaN
+ *   8-neighbours with their float32 median, each pass reading the previous
+ *   one, until no NaN is left, a pass changes nothing, or max_passes.  The
+ *   number of passes that met a NaN goes to *passes (host int, nullable).
+ *   Synchronises `stream` after every pass.
+ *   ws: graphic_workspace_size(GRAPHIC_OP_BADPIX_FIX) bytes (T N^2 floats
+ *   plus flags).
+ */
+graphic_status graphic_median_nan(graphic_ctx ctx, const graphic_geom* geom, const float* stack, float* out,
+                                  graphic_stream stream);
+graphic_status graphic_mask_disk(graphic_ctx ctx, const graphic_geom* geom, float* cube, const double* xs,
+                                 const double* ys, double radius, graphic_stream stream);
+graphic_status graphic_subtract_nearest(graphic_ctx ctx, const graphic_geom* geom, float* cube, const double* times,
+                                        const float* skies, const double* sky_times, int32_t n_skies,
+                                        graphic_stream stream);
+graphic_status graphic_badpix_map(graphic_ctx ctx, int32_t n, const float* frame, double c_sigma, uint8_t* map,
+                                  double* stats, void* ws, size_t ws_bytes, graphic_stream stream);
+graphic_status graphic_badpix_fix(graphic_ctx ctx, const graphic_geom* geom, float* cube, const uint8_t* map,
+                                  int32_t max_passes, int32_t* passes, void* ws, size_t ws_bytes,
+                                  graphic_stream stream);
 
 /*
  * Batched ADI reduction of cubes of uneven frame count and size (the

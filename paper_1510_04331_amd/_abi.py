@@ -12,14 +12,16 @@ LIB_PATH = os.path.join(HERE, "libgraphic.so")
 
 # status codes (graphic_status)
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM = range(6)
-OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN, OP_MEDIAN_WINDOW, OP_ADI_WINDOW = range(6)
+(OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN, OP_MEDIAN_WINDOW, OP_ADI_WINDOW, OP_BADPIX_MAP,
+ OP_BADPIX_FIX) = range(8)
 
 # every symbol that include/graphic.h declares
 EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
     "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_adi_reduce_window",
-    "graphic_parallactic_angles", "graphic_register",
+    "graphic_parallactic_angles", "graphic_register", "graphic_median_nan", "graphic_mask_disk",
+    "graphic_subtract_nearest", "graphic_badpix_map", "graphic_badpix_fix",
     "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
     "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
     "graphic_autotune", "graphic_tuning_export", "graphic_tuning_import",
@@ -95,6 +97,16 @@ def load():
     lib.graphic_parallactic_angles.restype = st
     lib.graphic_register.argtypes = [vp, g, vp, ctypes.POINTER(RegisterParams), vp, vp, vp]
     lib.graphic_register.restype = st
+    lib.graphic_median_nan.argtypes = [vp, g, vp, vp, vp]
+    lib.graphic_median_nan.restype = st
+    lib.graphic_mask_disk.argtypes = [vp, g, vp, vp, vp, f64, vp]
+    lib.graphic_mask_disk.restype = st
+    lib.graphic_subtract_nearest.argtypes = [vp, g, vp, vp, vp, vp, i32, vp]
+    lib.graphic_subtract_nearest.restype = st
+    lib.graphic_badpix_map.argtypes = [vp, i32, vp, f64, vp, vp, vp, sz, vp]
+    lib.graphic_badpix_map.restype = st
+    lib.graphic_badpix_fix.argtypes = [vp, g, vp, vp, i32, ctypes.POINTER(i32), vp, sz, vp]
+    lib.graphic_badpix_fix.restype = st
     cd = ctypes.POINTER(CubeDesc)
     lib.graphic_batch_workspace_size.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)]
     lib.graphic_batch_workspace_size.restype = st

@@ -633,6 +633,10 @@ graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geo
     case GRAPHIC_OP_MEDIAN_WINDOW:
       *bytes = window_sel_bytes(T);
       return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+    case GRAPHIC_OP_BADPIX_MAP: *bytes = frame_stats_ws_bytes(); return GRAPHIC_OK;
+    case GRAPHIC_OP_BADPIX_FIX:
+      *bytes = align_up((size_t)T * N * N * sizeof(float)) + kAlign;
+      return T > 65535 ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
     case GRAPHIC_OP_ADI_WINDOW:
       *bytes = align_up((size_t)T * N * N * sizeof(float)) + window_sel_bytes(T) + rot_layout(T, N, P, chunk, 0).total;
       return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
@@ -844,6 +848,99 @@ graphic_status graphic_register(graphic_ctx ctx, const graphic_geom* geom, const
   hipError_t e = launch_register(cube, geom->n_frames, geom->n, prm, out, flags, st);
   t.done();
   return hip_ok(e);
+}
+
+graphic_status graphic_median_nan(graphic_ctx ctx, const graphic_geom* geom, const float* stack, float* out,
+                                  graphic_stream stream) {
+  if (!ctx || !geom || !stack || !out) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames < 1 || geom->n < 1 || geom->flags != 0) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  if (overlap_bad(stack, out, (size_t)N * N * sizeof(float)) || (out >= stack && out < stack + (size_t)T * N * N))
+    return GRAPHIC_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Timer t(ctx, st, "median");
+  hipError_t e = launch_median_nan(stack, T, (long long)N * N, out, st);
+  t.done();
+  return hip_ok(e);
+}
+
+namespace {
+graphic_status frames_args(graphic_ctx ctx, const graphic_geom* geom, const void* cube) {
+  if (!ctx || !geom || !cube) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames < 1 || geom->n < 1 || geom->flags != 0) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames > 65535) return GRAPHIC_ERR_UNSUPPORTED;
+  return hipSetDevice(ctx->device) == hipSuccess ? GRAPHIC_OK : GRAPHIC_ERR_HIP;
+}
+}  // namespace
+
+graphic_status graphic_mask_disk(graphic_ctx ctx, const graphic_geom* geom, float* cube, const double* xs,
+                                 const double* ys, double radius, graphic_stream stream) {
+  graphic_status s = frames_args(ctx, geom, cube);
+  if (s != GRAPHIC_OK) return s;
+  if (!xs || !ys || std::isnan(radius)) return GRAPHIC_ERR_ARG;
+  return hip_ok(launch_mask_disk(cube, geom->n_frames, geom->n, xs, ys, radius, static_cast<hipStream_t>(stream)));
+}
+
+graphic_status graphic_subtract_nearest(graphic_ctx ctx, const graphic_geom* geom, float* cube, const double* times,
+                                        const float* skies, const double* sky_times, int32_t n_skies,
+                                        graphic_stream stream) {
+  graphic_status s = frames_args(ctx, geom, cube);
+  if (s != GRAPHIC_OK) return s;
+  if (!times || !skies || !sky_times || n_skies < 1) return GRAPHIC_ERR_ARG;
+  const size_t fb = (size_t)geom->n * geom->n * sizeof(float);
+  const char* c0 = reinterpret_cast<const char*>(cube);
+  const char* s0 = reinterpret_cast<const char*>(skies);
+  if (c0 < s0 + fb * (size_t)n_skies && s0 < c0 + fb * (size_t)geom->n_frames) return GRAPHIC_ERR_ARG;
+  return hip_ok(launch_subtract_nearest(cube, geom->n_frames, geom->n, times, skies, sky_times, n_skies,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+graphic_status graphic_badpix_map(graphic_ctx ctx, int32_t n, const float* frame, double c_sigma, uint8_t* map,
+                                  double* stats, void* ws, size_t ws_bytes, graphic_stream stream) {
+  if (!ctx || !frame || !map || n < 1 || std::isnan(c_sigma)) return GRAPHIC_ERR_ARG;
+  if (!ws_ok(ws, ws_bytes, frame_stats_ws_bytes())) return GRAPHIC_ERR_WORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  return hip_ok(launch_badpix_map(frame, n, c_sigma, map, stats, ws, static_cast<hipStream_t>(stream)));
+}
+
+graphic_status graphic_badpix_fix(graphic_ctx ctx, const graphic_geom* geom, float* cube, const uint8_t* map,
+                                  int32_t max_passes, int32_t* passes, void* ws, size_t ws_bytes,
+                                  graphic_stream stream) {
+  graphic_status s = frames_args(ctx, geom, cube);
+  if (s != GRAPHIC_OK) return s;
+  if (max_passes < 0) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t cube_b = align_up((size_t)T * N * N * sizeof(float));
+  if (!ws_ok(ws, ws_bytes, cube_b + kAlign)) return GRAPHIC_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* alt = static_cast<float*>(ws);
+  int* dflags = reinterpret_cast<int*>(static_cast<char*>(ws) + cube_b);
+  if (map && launch_apply_map(cube, T, N, map, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+  float* src = cube;
+  float* dst = alt;
+  int done = 0;
+  int hflags[2] = {0, 0};
+  for (int p = 0; p < max_passes; ++p) {
+    if (hipMemsetAsync(dflags, 0, 2 * sizeof(int), st) != hipSuccess) return GRAPHIC_ERR_HIP;
+    if (launch_repair_pass(src, dst, T, N, dflags, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+    if (hipMemcpyAsync(hflags, dflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return GRAPHIC_ERR_HIP;
+    std::swap(src, dst);                     // src now holds the pass's result
+    const bool left = hflags[0] != 0, changed = hflags[1] != 0;
+    if (!left && !changed) break;            // no NaN was there
+    ++done;
+    if (!left || !changed) break;
+  }
+  if (src != cube &&
+      hipMemcpyAsync(cube, src, (size_t)T * N * N * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return GRAPHIC_ERR_HIP;
+  if (passes) *passes = done;
+  return GRAPHIC_OK;
 }
 
 graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,

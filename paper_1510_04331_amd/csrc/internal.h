@@ -126,6 +126,20 @@ hipError_t launch_register(const float* cube, long long T, int n, const Register
 hipError_t launch_parallactic(const double* lst_s, long long T, double ra_deg, double dec_deg, double lat_deg,
                               double* out, hipStream_t s);
 
+// NaN-ignoring per-pixel median (NaN where no value is left), T <= 4096.
+hipError_t launch_median_nan(const float* stack, long long T, long long npix, float* out, hipStream_t s);
+
+// Pre-processing (Sect. 3.1-3.2); frames are indexed by the grid's y, T <= 65535.
+hipError_t launch_mask_disk(float* cube, long long T, int n, const double* xs, const double* ys, double radius,
+                            hipStream_t s);
+hipError_t launch_subtract_nearest(float* cube, long long T, int n, const double* times, const float* skies,
+                                   const double* sky_times, int S, hipStream_t s);
+size_t frame_stats_ws_bytes();
+hipError_t launch_badpix_map(const float* frame, int n, double c_sigma, unsigned char* map, double* stats, void* ws,
+                             hipStream_t s);
+hipError_t launch_apply_map(float* cube, long long T, int n, const unsigned char* map, hipStream_t s);
+hipError_t launch_repair_pass(const float* src, float* dst, long long T, int n, int* flags, hipStream_t s);
+
 // n floats of seeded noise around a sky level (for timing runs on scratch).
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
 

@@ -152,19 +152,20 @@ __device__ __forceinline__ void store_diff(const Tile<kPix>& t, float* resid, lo
 }
 
 // Exact median of the keys whose bit is set in `bits` (bit i: key[i]); K is
-// how many keys of the pixel take part (K >= 1).  Every thread of the block
-// calls it; on return sh.med[px] holds the median of every pixel.
-template <int VPT, int kPix>
+// how many keys of the pixel take part (K >= 1), the same for every pixel, or
+// with PPK per pixel in Kp[px] (LDS).  Every thread of the block calls it; on
+// return sh.med[px] holds the median of every pixel.
+template <int VPT, int kPix, bool PPK = false>
 __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigned (&key)[VPT],
                                               unsigned long long bits, unsigned K, unsigned* hist,
-                                              SelShared<kPix>& sh) {
+                                              SelShared<kPix>& sh, const unsigned* Kp = nullptr) {
   constexpr int kThreads = kPix * kGroups;
   constexpr int kSub = 64 / kPix;
   unsigned* my_hist = hist + (t.px * kSub + t.sub) * kHistWords;
-  const unsigned k_lo = (K - 1) / 2;
   if (t.tid < kPix) {
+    const unsigned Kt = PPK ? Kp[t.tid] : K;
     sh.prefix[t.tid] = 0u;
-    sh.rank[t.tid] = k_lo;
+    sh.rank[t.tid] = Kt == 0u ? 0u : (Kt - 1u) / 2u;
     sh.lo[t.tid] = 0xFFFFFFFFu;
   }
   unsigned mask = 0u;
@@ -252,7 +253,9 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
   atomicMin(&sh.min[t.px], local_min);
   __syncthreads();
   if (t.g == 0) {
-    const unsigned step = K / 2 - k_lo;                  // 0 (odd K) or 1
+    const unsigned Kx = PPK ? Kp[t.px] : K;
+    const unsigned k_lo = Kx == 0u ? 0u : (Kx - 1u) / 2u;
+    const unsigned step = Kx / 2 - k_lo;                 // 0 (odd K) or 1
     const float lo = val_of(lo_key);
     const float hi = (sh.rank[t.px] + step < sh.cnt[t.px]) ? lo : val_of(sh.min[t.px]);
     sh.med[t.px] = (lo + hi) * 0.5f;
@@ -312,6 +315,30 @@ median_window_kernel(const float* __restrict__ stack, long long T, long long npi
     }
   }
   if (resid != nullptr) store_diff<VPT, kPix, BUF>(t, resid, npix, key, med_own);
+}
+
+// Per-pixel median ignoring NaN values (the master sky of Sect. 3.1: star
+// regions are NaN); a pixel with no value left is NaN.
+template <int VPT, bool BUF>
+__global__ void __launch_bounds__(16 * kGroups) median_nan_kernel(const float* __restrict__ stack, long long T,
+                                                                  long long npix, float* __restrict__ out) {
+  constexpr int kPix = 16;
+  extern __shared__ unsigned hist[];
+  __shared__ SelShared<kPix> sh;
+  __shared__ unsigned s_K[kPix];
+  const Tile<kPix> t(T, npix);
+  unsigned key[VPT];
+  load_keys<VPT, kPix, BUF>(t, stack, npix, key);      // frames past T get a NaN key
+  unsigned long long bits = 0ull;
+#pragma unroll
+  for (int i = 0; i < VPT; ++i)
+    if (!isnan(val_of(key[i]))) bits |= 1ull << i;
+  if (t.tid < kPix) s_K[t.tid] = 0u;
+  __syncthreads();
+  atomicAdd(&s_K[t.px], (unsigned)__popcll(bits));
+  __syncthreads();
+  select_median<VPT, kPix, true>(t, key, bits, 0u, hist, sh, s_K);
+  if (t.g == 0 && t.pix_ok) out[t.pix] = s_K[t.px] == 0u ? __int_as_float(0x7FC00000) : sh.med[t.px];
 }
 
 // Frame selection of the per-frame PSF: row f marks the frames k with
@@ -417,6 +444,38 @@ hipError_t launch_median_window(const float* stack, long long T, long long npix,
   GRAPHIC_WINDOW_CASE(32)
 #undef GRAPHIC_WINDOW_CASE
   return hipErrorInvalidValue;   // T > 2048: rejected on the host before launch
+}
+
+hipError_t launch_median_nan(const float* stack, long long T, long long npix, float* out, hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  const long long vpt = (T + kGroups - 1) / kGroups;
+  const unsigned blocks = (unsigned)((npix + 15) / 16);
+  const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
+  const size_t lds = (size_t)16 * 4 * kHistWords * sizeof(unsigned);
+#define GRAPHIC_NAN_CASE(V)                                                                                 \
+  if (vpt <= V) {                                                                                          \
+    if (buf) {                                                                                             \
+      hipFuncSetAttribute((const void*)median_nan_kernel<V, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                          (int)lds);                                                                       \
+      hipLaunchKernelGGL((median_nan_kernel<V, true>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T, npix, \
+                         out);                                                                             \
+    } else {                                                                                               \
+      hipFuncSetAttribute((const void*)median_nan_kernel<V, false>,                                        \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      hipLaunchKernelGGL((median_nan_kernel<V, false>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T,  \
+                         npix, out);                                                                       \
+    }                                                                                                      \
+    return hipGetLastError();                                                                              \
+  }
+  GRAPHIC_NAN_CASE(1)
+  GRAPHIC_NAN_CASE(2)
+  GRAPHIC_NAN_CASE(4)
+  GRAPHIC_NAN_CASE(8)
+  GRAPHIC_NAN_CASE(16)
+  GRAPHIC_NAN_CASE(32)
+  GRAPHIC_NAN_CASE(64)
+#undef GRAPHIC_NAN_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid, int variant,

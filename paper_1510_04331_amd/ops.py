@@ -256,6 +256,72 @@ def register(cube, threshold, min_size, max_size, half=16, saturation=float("inf
     return res
 
 
+def median_nan(stack, out=None):
+    """Per-pixel median over axis 0 ignoring NaN (NaN where none is left)."""
+    import torch
+    T, N = _check_cube(stack, "stack")
+    out = torch.empty((N, N), dtype=torch.float32, device=stack.device) if out is None else out
+    g = _geom(T, N, 0)
+    _abi.check(_abi.load().graphic_median_nan(context(stack.device.index or 0), ctypes.byref(g), _ptr(stack),
+                                              _ptr(out), _stream(stack.device)), "graphic_median_nan")
+    return out
+
+
+def mask_disk(cube, xs, ys, radius):
+    """NaN out, in place, the disc of ``radius`` around (xs[i], ys[i]) in frame i."""
+    T, N = _check_cube(cube)
+    dev = cube.device
+    x, y = _f64(xs, T, dev, "xs"), _f64(ys, T, dev, "ys")
+    g = _geom(T, N, 0)
+    _abi.check(_abi.load().graphic_mask_disk(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(x), _ptr(y),
+                                             float(radius), _stream(dev)), "graphic_mask_disk")
+    return cube
+
+
+def subtract_nearest(cube, times, skies, sky_times):
+    """In place: every frame minus the sky closest to it in time."""
+    T, N = _check_cube(cube)
+    S, Ns = _check_cube(skies, "skies")
+    if Ns != N:
+        raise ValueError("skies must have the frames' size")
+    dev = cube.device
+    t, st_ = _f64(times, T, dev, "times"), _f64(sky_times, S, dev, "sky_times")
+    g = _geom(T, N, 0)
+    _abi.check(_abi.load().graphic_subtract_nearest(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(t),
+                                                    _ptr(skies), _ptr(st_), S, _stream(dev)),
+               "graphic_subtract_nearest")
+    return cube
+
+
+def badpix_map(frame, c_sigma):
+    """Bad pixel map of one N x N frame and its (median, mean, sigma)."""
+    import torch
+    if frame.dim() != 2 or frame.shape[0] != frame.shape[1] or frame.dtype != torch.float32 or not frame.is_contiguous():
+        raise ValueError("frame must be a contiguous float32 [N, N] tensor")
+    N = frame.shape[0]
+    dev = frame.device
+    m = torch.empty((N, N), dtype=torch.uint8, device=dev)
+    stats = torch.empty(3, dtype=torch.float64, device=dev)
+    ws, n = _workspace(_abi.OP_BADPIX_MAP, 1, 8, 0, dev)
+    _abi.check(_abi.load().graphic_badpix_map(context(dev.index or 0), N, _ptr(frame), float(c_sigma), _ptr(m),
+                                              _ptr(stats), _ptr(ws), n, _stream(dev)), "graphic_badpix_map")
+    return m, stats
+
+
+def badpix_fix(cube, bad_map=None, max_passes=64):
+    """In place: flagged pixels to NaN, then neighbour-median repair passes.
+    Returns the number of passes that met a NaN."""
+    T, N = _check_cube(cube)
+    dev = cube.device
+    ws, n = _workspace(_abi.OP_BADPIX_FIX, T, N, 0, dev)
+    passes = ctypes.c_int32()
+    g = _geom(T, N, 0)
+    _abi.check(_abi.load().graphic_badpix_fix(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(bad_map),
+                                              int(max_passes), ctypes.byref(passes), _ptr(ws), n, _stream(dev)),
+               "graphic_badpix_fix")
+    return passes.value
+
+
 def _batch_descs(cubes, dx, dy, parang, pad, psf, residuals):
     import torch
     n = len(cubes)

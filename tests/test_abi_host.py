@@ -92,3 +92,20 @@ def test_window_workspace_sizes(lib):
     big = _abi.Geom(2049, 64, 0, 0)       # the per-frame PSF holds up to 2048 frames
     for op in (_abi.OP_MEDIAN_WINDOW, _abi.OP_ADI_WINDOW):
         assert lib.graphic_workspace_size(None, op, ctypes.byref(big), ctypes.byref(sz)) == _abi.ERR_UNSUPPORTED
+
+
+def test_preprocess_and_register_reject_bad_arguments(lib):
+    g = _abi.Geom(2, 8, 0, 0)
+    assert lib.graphic_median_nan(None, ctypes.byref(g), None, None, None) == _abi.ERR_ARG
+    assert lib.graphic_mask_disk(None, ctypes.byref(g), None, None, None, 1.0, None) == _abi.ERR_ARG
+    assert lib.graphic_subtract_nearest(None, ctypes.byref(g), None, None, None, None, 1, None) == _abi.ERR_ARG
+    assert lib.graphic_badpix_map(None, 8, None, 5.0, None, None, None, 0, None) == _abi.ERR_ARG
+    assert lib.graphic_badpix_fix(None, ctypes.byref(g), None, None, 4, None, None, 0, None) == _abi.ERR_ARG
+    prm = _abi.RegisterParams(1.0, 1, 10, 16, 50, float("inf"))
+    assert lib.graphic_register(None, ctypes.byref(g), None, ctypes.byref(prm), None, None, None) == _abi.ERR_ARG
+    assert lib.graphic_parallactic_angles(None, None, 1, 0.0, 0.0, 0.0, None, None) == _abi.ERR_ARG
+    sz = ctypes.c_size_t()
+    assert lib.graphic_workspace_size(None, _abi.OP_BADPIX_MAP, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 256 * 256 * 4
+    assert lib.graphic_workspace_size(None, _abi.OP_BADPIX_FIX, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
+    assert sz.value >= 2 * 8 * 8 * 4

@@ -1,0 +1,96 @@
+"""GPU: image pre-processing (Sect. 3.1-3.2) against the oracle, bit for
+bit: star masks, the NaN-aware master-sky median, nearest-sky subtraction,
+the sigma-clipped bad pixel map (median exact, sigma to rounding) and the
+neighbour repair passes."""
+
+import numpy as np
+import pytest
+
+from oracle import preprocess as Q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+def _same(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return a.shape == b.shape and np.array_equal(np.isnan(a), np.isnan(b)) and \
+        a[~np.isnan(a)].tobytes() == b[~np.isnan(b)].tobytes()
+
+
+@pytest.mark.parametrize("T,N", [(1, 8), (7, 6), (64, 8), (100, 10), (700, 6)])
+def test_median_nan(torch_dev, T, N):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    rng = np.random.default_rng(T)
+    st = (rng.normal(size=(T, N, N)) * 3).astype(np.float32)
+    st[rng.random(st.shape) < 0.3] = np.nan
+    st[:, 0, 0] = np.nan                                  # nothing left
+    st[:, 0, 1] = np.round(st[:, 0, 1])                   # ties
+    got = G.median_nan(torch.from_numpy(st).to(dev)).cpu().numpy()
+    assert _same(got, Q.median_nan_f32(st))
+
+
+def test_mask_and_nearest_sky(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    rng = np.random.default_rng(5)
+    T, N = 12, 32
+    cube = (rng.normal(size=(T, N, N)) + 100).astype(np.float32)
+    xs, ys = rng.uniform(8, 24, T), rng.uniform(8, 24, T)
+    x = torch.from_numpy(cube).to(dev)
+    G.mask_disk(x, xs, ys, 5.5)
+    ref = Q.mask_disk(cube, xs, ys, 5.5)
+    assert _same(x.cpu().numpy(), ref)
+    # master skies from groups of 4 time-contiguous masked frames, then subtraction
+    skies = torch.stack([G.median_nan(x[4 * k:4 * k + 4].contiguous()) for k in range(3)])
+    ref_skies = np.stack([Q.median_nan_f32(ref[4 * k:4 * k + 4]) for k in range(3)])
+    assert _same(skies.cpu().numpy(), ref_skies)
+    times = np.arange(T, dtype=np.float64)
+    sky_times = np.array([1.5, 5.5, 9.5])
+    sci = torch.from_numpy(cube).to(dev)
+    G.subtract_nearest(sci, times, torch.from_numpy(np.nan_to_num(ref_skies)).to(dev), sky_times)
+    assert _same(sci.cpu().numpy(), Q.subtract_nearest(cube, times, np.nan_to_num(ref_skies), sky_times))
+
+
+def test_badpix_map(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    rng = np.random.default_rng(8)
+    for N in (16, 200):
+        f = rng.normal(50.0, 3.0, (N, N)).astype(np.float32)
+        f[rng.random((N, N)) < 0.01] = 5000.0             # hot pixels
+        f[3, 4] = np.nan
+        f[5, 5] = -np.inf
+        m, stats = G.badpix_map(torch.from_numpy(f).to(dev), 5.0)
+        assert np.array_equal(m.cpu().numpy().astype(bool), Q.badpix_map(f, 5.0))
+        fin = f[np.isfinite(f)]
+        s = stats.cpu().numpy()
+        assert np.float32(s[0]) == Q.median_nan_f32(fin[:, None, None])[0, 0]
+        assert abs(s[2] - np.std(fin.astype(np.float64))) <= 1e-12 * s[2]
+
+
+def test_badpix_fix(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    rng = np.random.default_rng(9)
+    T, N = 5, 40
+    cube = rng.normal(20.0, 2.0, (T, N, N)).astype(np.float32)
+    bad = rng.random((N, N)) < 0.03
+    bad[10:15, 20:24] = True                              # a clump
+    bad[0, :] = True                                      # a full border row
+    cube[2, 30, 30] = np.nan                              # a NaN of one frame only
+    x = torch.from_numpy(cube).to(dev)
+    passes = G.badpix_fix(x, torch.from_numpy(bad.astype(np.uint8)).to(dev))
+    ref, ref_passes = Q.badpix_fix(cube, bad)
+    assert passes == ref_passes
+    assert _same(x.cpu().numpy(), ref)
+    assert G.badpix_fix(x) == 0                           # nothing left to repair
