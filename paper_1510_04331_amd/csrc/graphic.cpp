@@ -66,6 +66,8 @@ struct graphic_ctx_s {
   };
   std::vector<Acc> acc;
   size_t chunk_bytes = kDefaultChunkBytes;
+  bool tile_major = true;                 // workspace stacks of the large canonical sizes are tile-major
+  int frame_group = 64;                   // block order of the passes over tile-major stacks
   // tuned launch variants (-1: not tuned, the default variant 0 runs)
   int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass
   int med_var[8];                         // [log2 of the median's values per thread]
@@ -260,7 +262,9 @@ struct RotItem {
 
 // Shift (Sect. 3.3.1): column pass (content moves by dy along y) then row pass
 // (dx along x); up to kMaxCubesPerLaunch cubes per launch.
-graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it, int n, hipStream_t st) {
+// With tm the outputs are tile-major stacks (the inputs stay frame-major).
+graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it, int n, hipStream_t st,
+                              bool tm = false) {
   const int o = (P - N) / 2;
   for (int i0 = 0; i0 < n; i0 += kMaxCubesPerLaunch) {
     const int g = std::min(kMaxCubesPerLaunch, n - i0);
@@ -280,17 +284,20 @@ graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it
     c.n_cubes = g;
     long long F = 0;
     for (int k = 0; k < g; ++k) {
-      c.cubes[k] = CubeRef{it[i0 + k].in, it[i0 + k].out, it[i0 + k].dy, F};
+      c.cubes[k] = CubeRef{it[i0 + k].in, it[i0 + k].out, it[i0 + k].dy, F, it[i0 + k].T};
       F += it[i0 + k].T;
     }
     c.n_frames = F;
+    c.dst_tm = tm ? 1 : 0;
+    c.frame_group = tm ? ctx->frame_group : 0;
     graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
     if (s != GRAPHIC_OK) return s;
     LinePass r = c;
     r.src_ls = r.dst_ls = N;
     r.src_ps = r.dst_ps = 1;
+    r.src_tm = r.dst_tm = tm ? 1 : 0;
     for (int k = 0; k < g; ++k)
-      r.cubes[k] = CubeRef{it[i0 + k].out, it[i0 + k].out, it[i0 + k].dx, c.cubes[k].frame0};
+      r.cubes[k] = CubeRef{it[i0 + k].out, it[i0 + k].out, it[i0 + k].dx, c.cubes[k].frame0, it[i0 + k].T};
     if ((s = run_pass(ctx, r, kRowPass, "shift_x", st)) != GRAPHIC_OK) return s;
   }
   return GRAPHIC_OK;
@@ -298,9 +305,10 @@ graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it
 
 // Three-shear rotation (Sect. 3.4) of every frame of the class, chunked over
 // the concatenated frames; a chunk may span cubes (at most
-// kMaxCubesPerLaunch of them).  dst may alias src.
+// kMaxCubesPerLaunch of them).  dst may alias src.  With tm, src and dst are
+// tile-major stacks.
 graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it, int n, double sign, void* ws,
-                               size_t ws_bytes, hipStream_t st) {
+                               size_t ws_bytes, hipStream_t st, bool tm = false) {
   long long F = 0;
   std::vector<long long> start(n + 1, 0);
   for (int i = 0; i < n; ++i) {
@@ -365,7 +373,10 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
     a.flip_lines = 1;
     a.flip_in_off = 1;
     a.n_cubes = ncub;
-    for (int k = 0; k < ncub; ++k) a.cubes[k] = CubeRef{it[c0 + k].src, nullptr, nullptr, start[c0 + k] - f0};
+    for (int k = 0; k < ncub; ++k)
+      a.cubes[k] = CubeRef{it[c0 + k].src, nullptr, nullptr, start[c0 + k] - f0, it[c0 + k].T};
+    a.src_tm = tm ? 1 : 0;
+    a.frame_group = tm ? ctx->frame_group : 0;
     graphic_status s = run_pass(ctx, a, kRowPass, "shear_x1", st);
     if (s != GRAPHIC_OK) return s;
     // y-shear: every scratch column, window rows in and out (in place)
@@ -412,7 +423,10 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
     c.n_frames = nf;
     c.sh1 = ntan + f0;
     c.n_cubes = ncub;
-    for (int k = 0; k < ncub; ++k) c.cubes[k] = CubeRef{nullptr, it[c0 + k].dst, nullptr, start[c0 + k] - f0};
+    for (int k = 0; k < ncub; ++k)
+      c.cubes[k] = CubeRef{nullptr, it[c0 + k].dst, nullptr, start[c0 + k] - f0, it[c0 + k].T};
+    c.dst_tm = tm ? 1 : 0;
+    c.frame_group = tm ? ctx->frame_group : 0;
     if ((s = run_pass(ctx, c, kRowPass, "shear_x2", st)) != GRAPHIC_OK) return s;
     f0 += nf;
   }
@@ -420,9 +434,10 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
 }
 
 graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, float* resid,
-                         hipStream_t st) {
+                         hipStream_t st, bool tm = false) {
   Timer t(ctx, st, "median");
-  hipError_t e = launch_median(stack, T, (long long)N * N, out, resid, median_variant(ctx, T), st);
+  hipError_t e = tm ? launch_median_tile_major(stack, T, (long long)N * N, out, resid, st)
+                    : launch_median(stack, T, (long long)N * N, out, resid, median_variant(ctx, T), st);
   t.done();
   return hip_ok(e);
 }
@@ -529,21 +544,27 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
     const int N = d[c[0]].n, P = plan.P[c[0]];
     std::vector<ShiftItem> sh;
     std::vector<RotItem> rot;
+    // Stacks that only the workspace holds are kept tile-major when the
+    // class has the canonical large geometry (P = 2N, N >= 1024): the
+    // medians then stream each 16-pixel run of the stack contiguously.
+    bool tm = ctx->tile_major && P == 2 * N && N >= 1024 && N <= kMaxM;
     for (int i : c) {
       sh.push_back(ShiftItem{d[i].cube, stack[i], d[i].n_frames, d[i].dx, d[i].dy});
       rot.push_back(RotItem{stack[i], stack[i], d[i].n_frames, d[i].parang_deg});
+      tm = tm && plan.stack_off[i] != SIZE_MAX && (long long)N * 4 * d[i].n_frames <= 0x7fffffffLL;
     }
     // S_i = shift(cube_i): every cube of the class in the same launches
-    if ((s = do_shift_batch(ctx, N, P, sh.data(), (int)sh.size(), st)) != GRAPHIC_OK) return s;
+    if ((s = do_shift_batch(ctx, N, P, sh.data(), (int)sh.size(), st, tm)) != GRAPHIC_OK) return s;
     // PSF = median_i S_i; the median also rewrites the stack as S_i - PSF
     for (int i : c)
-      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], psf[i], stack[i], st)) != GRAPHIC_OK) return s;
+      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], psf[i], stack[i], st, tm)) != GRAPHIC_OK) return s;
     // D_i = rotate(S_i - PSF, -parang_i), in place
-    if ((s = do_rotate_batch(ctx, N, P, rot.data(), (int)rot.size(), -1.0, rot_ws, rot_bytes, st)) != GRAPHIC_OK)
+    if ((s = do_rotate_batch(ctx, N, P, rot.data(), (int)rot.size(), -1.0, rot_ws, rot_bytes, st, tm)) !=
+        GRAPHIC_OK)
       return s;
     // final = median_i D_i
     for (int i : c)
-      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], d[i].final_img, nullptr, st)) != GRAPHIC_OK) return s;
+      if ((s = do_median(ctx, d[i].n_frames, N, stack[i], d[i].final_img, nullptr, st, tm)) != GRAPHIC_OK) return s;
   }
   return GRAPHIC_OK;
 }
@@ -585,6 +606,11 @@ graphic_status graphic_create(graphic_ctx* out, int hip_device) {
   if (const char* env = std::getenv("GRAPHIC_ROTATE_CHUNK_MB")) {
     long v = std::atol(env);
     if (v > 0) c->chunk_bytes = (size_t)v << 20;
+  }
+  if (const char* env = std::getenv("GRAPHIC_TILE_MAJOR")) c->tile_major = std::atoi(env) != 0;
+  if (const char* env = std::getenv("GRAPHIC_FRAME_GROUP")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 4096) c->frame_group = v;
   }
   graphic_status s = build_tables(c);
   if (s != GRAPHIC_OK) {

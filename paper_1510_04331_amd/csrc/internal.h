@@ -22,6 +22,13 @@ struct TwiddleTables {
 
 constexpr int kMaxCubesPerLaunch = 16;
 
+// Tile-major stack layout: the value of frame t at pixel p (row-major pixel
+// index of an N x N frame) of a T-frame stack sits at float index
+// ((p / 16) * T + t) * 16 + p % 16, so the T values of 16 neighbouring pixels
+// are one contiguous run of 64 T bytes.  The ADI reduction keeps its
+// workspace stack in this layout for the large canonical sizes.
+constexpr int kTilePix = 16;
+
 // One cube of a batched launch: frames [frame0, frame0 + n) of the launch
 // belong to it (frame0 may be negative when the launch starts inside it).
 // A null member means "the launch's own array, indexed by the launch frame".
@@ -30,6 +37,7 @@ struct CubeRef {
   float* dst;             // the cube's frame 0 in the pass's destination, or null
   const double* sh0;      // the cube's per-frame constant shift (local frame index), or null
   long long frame0;
+  long long tm_T;         // frames of the cube (tile-major source or destination only)
 };
 
 // One pass of one-dimensional Fourier shifts over the lines of a stack of
@@ -54,6 +62,14 @@ struct LinePass {
   int n_jobs;             // jobs (line pairs) per frame
   long long n_frames;
   int blocks_per_frame;   // set by the launcher: blocks never straddle frames
+  int frame_group;        // block order: 0 or 1 = frame by frame; g > 1 = the blocks of g
+                          // consecutive frames interleaved, frame fastest
+
+  // Tile-major cube arrays (cube launches only, rows of N = P/2 >= 1024
+  // pixels, window-to-window or window-to-full index patterns): the source
+  // (src_tm) or destination (dst_tm) of every cube is a tile-major stack of
+  // cubes[i].tm_T frames; *_fs, *_ls and *_ps are ignored for it.
+  int src_tm, dst_tm;
 
   // Batched launches: with n_cubes > 0, frame f of the launch lives in the
   // cube with the largest frame0 <= f, and src/dst/sh0 come from that cube
@@ -100,6 +116,10 @@ hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* lis
 // variant: 0 = 16-pixel tiles, 1 = 8-pixel tiles (same result).
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
                          int variant, hipStream_t s);
+// The same on a tile-major stack (npix a multiple of 16; resid, if non-null,
+// is tile-major too and may be stack).
+hipError_t launch_median_tile_major(const float* stack, long long T, long long npix, float* out, float* resid,
+                                    hipStream_t s);
 
 // Frame selection of the per-frame PSF (sel: [T][64] bit rows, counts: [T]).
 hipError_t launch_select_frames(const double* times, const double* parang, long long T, double t_max,

@@ -202,11 +202,21 @@ constexpr int lds_floats() {
 // wave-level ordering; the block first copies its 2G source columns (the
 // window rows) into an LDS tile with row-contiguous loads, and writes its
 // results back through the same tile with row-contiguous stores.
-template <int M, int KIND, int G, int IO, bool MIR, bool STG = false>
+//
+// TM (bit 0: source, bit 1: destination) selects tile-major cube arrays: a
+// row of the frame is then M / 16 chunks of 16 pixels, cs = 64 T bytes apart,
+// and each of the job's two rows gets its own wave-uniform descriptor (row
+// passes with M >= 1024 run one job per wave).
+template <int M, int KIND, int G, int IO, bool MIR, bool STG = false, int TM = 0>
 __device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
   static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
+  constexpr bool TMS = (TM & 1) != 0, TMD = (TM & 2) != 0;
+  static_assert(!TM || (M >= 1024 && (KIND == kColPass || G * JOB == 64)), "tile-major rows: one job per wave");
+  static_assert(!TMS || KIND == kRowPass, "tile-major sources are read by row passes");
+  static_assert(!TMD || (KIND == kRowPass ? (IO == kIoWinWin || IO == kIoFullWin) : STG),
+                "tile-major destinations: window stores of row passes or staged column stores");
   // Column blocks span several waves: their exchanges use separate buffers
   // for real and imaginary parts, so each exchange needs one barrier.  Row
   // blocks are one wave (barriers are free, LDS bounds occupancy): one buffer.
@@ -287,6 +297,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   float* dst_base = p.dst;
   const double* sh0 = p.sh0;
   long long fsrc = f, fdst = f, fsh = f;
+  long long tmT = 1;
   if (p.n_cubes > 0) {
     int ci = 0;
     for (int q2 = 1; q2 < p.n_cubes; ++q2)
@@ -295,6 +306,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     if (p.cubes[ci].src) { src_base = p.cubes[ci].src; fsrc = fl; }
     if (p.cubes[ci].dst) { dst_base = p.cubes[ci].dst; fdst = fl; }
     if (p.cubes[ci].sh0) { sh0 = p.cubes[ci].sh0; fsh = fl; }
+    tmT = p.cubes[ci].tm_T;
   }
   double s = 0.0;
   if (sh0) s += sh0[fsh];
@@ -316,8 +328,20 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const __amdgpu_buffer_rsrc_t tinv = make_rsrc(p.tw.inv, (unsigned)M * 8u);
   const unsigned ls4 = (unsigned)p.src_ls * 4u;
   const int ps4 = p.src_ps * 4;
-  const unsigned base_a = a_ok ? (unsigned)lia * ls4 : kOOB;
-  const unsigned base_b = b_ok ? (unsigned)lib * ls4 : kOOB;
+  // tile-major arrays: byte offset of row position x from the row's first
+  // chunk, and the descriptor of row y of local frame fl (its M / 16 chunks)
+  const unsigned cs = (unsigned)(tmT * 64);
+  auto tmo = [&](int x) -> unsigned { return (unsigned)(x >> 4) * cs + (unsigned)(x & 15) * 4u; };
+  auto tm_row = [&](const float* base, long long fl, int y) {
+    const int yu = __builtin_amdgcn_readfirstlane(y);
+    return make_rsrc(base + ((long long)yu * (M / kTilePix) * tmT + fl) * kTilePix,
+                     (unsigned)(M / kTilePix - 1) * cs + 64u);
+  };
+  auto off_src = [&](int x) -> unsigned { return TMS ? tmo(x) : (unsigned)(x * ps4); };
+  const __amdgpu_buffer_rsrc_t srcA = TMS ? tm_row(src_base, fsrc, a_ok ? lia : 0) : src;
+  const __amdgpu_buffer_rsrc_t srcB = TMS ? tm_row(src_base, fsrc, b_ok ? lib : 0) : src;
+  const unsigned base_a = a_ok ? (TMS ? 0u : (unsigned)lia * ls4) : kOOB;
+  const unsigned base_b = b_ok ? (TMS ? 0u : (unsigned)lib * ls4) : kOOB;
   // the canonical geometries (P = 2N, frame not half-turned) use static
   // index patterns; everything else takes the general path
   constexpr bool fast = IO != kIoGeneric;
@@ -382,29 +406,29 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   } else if constexpr (fast && (IO == kIoWinWin || IO == kIoWinFull)) {
     // support [M/2, 3M/2): element m = n1 + Ma n2 has exactly one valid
     // candidate, position u = n1 + Ma ((n2 + Mb/2) mod Mb) of the source line
-    const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
-    const unsigned lb_lane = base_b + (unsigned)((MIR ? (Ma - 1 - n1) : n1) * ps4);
+    const unsigned la_lane = base_a + off_src(n1);
+    const unsigned lb_lane = base_b + off_src(MIR ? (Ma - 1 - n1) : n1);
 #pragma unroll
     for (int n2 = 0; n2 < Mb; ++n2) {
       const int k = (n2 + Mb / 2) % Mb;
-      const int sa = Ma * k * ps4;
-      const int sb = (MIR ? Ma * (Mb - 1 - k) : Ma * k) * ps4;
-      const float av = buf_ld(src, la_lane, sa), bv = buf_ld(src, lb_lane, sb);
+      const int sa = (int)off_src(Ma * k);
+      const int sb = (int)off_src(MIR ? Ma * (Mb - 1 - k) : Ma * k);
+      const float av = buf_ld(srcA, la_lane, sa), bv = buf_ld(srcB, lb_lane, sb);
       const float sc = n2 < Mb / 2 ? sg : 1.0f;    // the valid candidate is n = m + M below Mb/2
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({sc * av, sc * bv}, w);
     }
   } else if constexpr (fast && IO == kIoFullWin) {
     // support [0, P): both candidates n = m and n = m + M are valid
-    const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
-    const unsigned lb_lane = base_b + (unsigned)((MIR ? (Ma - 1 - n1) : n1) * ps4);
+    const unsigned la_lane = base_a + off_src(n1);
+    const unsigned lb_lane = base_b + off_src(MIR ? (Ma - 1 - n1) : n1);
 #pragma unroll
     for (int n2 = 0; n2 < Mb; ++n2) {
-      const int sa0 = Ma * n2 * ps4, sa1 = (Ma * n2 + M) * ps4;
-      const int sb0 = (MIR ? Ma * (2 * Mb - 1 - n2) : Ma * n2) * ps4;
-      const int sb1 = (MIR ? Ma * (Mb - 1 - n2) : Ma * n2 + M) * ps4;
-      const float a0 = buf_ld(src, la_lane, sa0), a1 = buf_ld(src, la_lane, sa1);
-      const float b0 = buf_ld(src, lb_lane, sb0), b1 = buf_ld(src, lb_lane, sb1);
+      const int sa0 = (int)off_src(Ma * n2), sa1 = (int)off_src(Ma * n2 + M);
+      const int sb0 = (int)off_src(MIR ? Ma * (2 * Mb - 1 - n2) : Ma * n2);
+      const int sb1 = (int)off_src(MIR ? Ma * (Mb - 1 - n2) : Ma * n2 + M);
+      const float a0 = buf_ld(srcA, la_lane, sa0), a1 = buf_ld(srcA, la_lane, sa1);
+      const float b0 = buf_ld(srcB, lb_lane, sb0), b1 = buf_ld(srcB, lb_lane, sb1);
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({fmaf(sg, a1, a0), fmaf(sg, b1, b0)}, w);
     }
@@ -420,9 +444,9 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
         const bool in = u < L;
         const unsigned pa = (unsigned)(rev ? (L - 1 - u) : u);
         const unsigned pb = (unsigned)(rev_b ? (L - 1 - u) : u);
-        const unsigned oa = in ? base_a + pa * (unsigned)ps4 : kOOB;
-        const unsigned ob = in ? base_b + pb * (unsigned)ps4 : kOOB;
-        z[cnd] = {buf_ld(src, oa), buf_ld(src, ob)};
+        const unsigned oa = in ? base_a + off_src((int)pa) : kOOB;
+        const unsigned ob = in ? base_b + off_src((int)pb) : kOOB;
+        z[cnd] = {buf_ld(srcA, oa), buf_ld(srcB, ob)};
       }
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
@@ -523,8 +547,13 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   const int dst_lo = p.dst_line_lo + (p.flip_lines ? flipf : 0);
   const unsigned dls4 = (unsigned)p.dst_ls * 4u;
   const int dps4 = p.dst_ps * 4;
-  const unsigned obase_a = a_ok ? (unsigned)((la - dst_lo + P) & (P - 1)) * dls4 : kOOB;
-  const unsigned obase_b = b_ok ? (unsigned)((lb2 - dst_lo + P) & (P - 1)) * dls4 : kOOB;
+  const int orow_a = (la - dst_lo + P) & (P - 1), orow_b = (lb2 - dst_lo + P) & (P - 1);
+  const unsigned obase_a = a_ok ? (TMD ? 0u : (unsigned)orow_a * dls4) : kOOB;
+  const unsigned obase_b = b_ok ? (TMD ? 0u : (unsigned)orow_b * dls4) : kOOB;
+  auto off_dst = [&](int x) -> unsigned { return TMD ? tmo(x) : (unsigned)(x * dps4); };
+  constexpr bool TMDR = TMD && KIND == kRowPass;
+  const __amdgpu_buffer_rsrc_t dstA = TMDR ? tm_row(dst_base, fdst, a_ok ? orow_a : 0) : dst;
+  const __amdgpu_buffer_rsrc_t dstB = TMDR ? tm_row(dst_base, fdst, b_ok ? orow_b : 0) : dst;
   if constexpr (DB) {
     xsync();
 #pragma unroll
@@ -568,10 +597,19 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       int rk;
       bool ok;
       slot_line(sl, rk, ok, true);
-      const unsigned lbase = ok ? (unsigned)rk * dls4 : kOOB;
+      if constexpr (TMD) {
+        // column rk of a tile-major stack: its rows are M / 16 chunks apart
+        float* col = dst_base + ((long long)(rk >> 4) * tmT + fdst) * kTilePix + (rk & 15);
+        const long long rstep = (long long)(M / kTilePix) * tmT * kTilePix;
 #pragma unroll 8
-      for (int u = tid / (2 * G); u < M; u += JOB / 2)
-        buf_st(dst, ok ? lbase + (unsigned)(u * dps4) : kOOB, stg[u * SP + sl]);
+        for (int u = tid / (2 * G); u < M; u += JOB / 2)
+          if (ok) col[u * rstep] = stg[u * SP + sl];
+      } else {
+        const unsigned lbase = ok ? (unsigned)rk * dls4 : kOOB;
+#pragma unroll 8
+        for (int u = tid / (2 * G); u < M; u += JOB / 2)
+          buf_st(dst, ok ? lbase + (unsigned)(u * dps4) : kOOB, stg[u * SP + sl]);
+      }
     }
     return;
   }
@@ -585,17 +623,18 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     }
     const int pb = DB ? part * BUF : 0;
     const unsigned obase = part ? obase_b : obase_a;
+    const __amdgpu_buffer_rsrc_t dd = part ? dstB : dstA;
     if constexpr (fast && (IO == kIoWinWin || IO == kIoFullWin)) {
       // window [M/2, 3M/2): half h writes n2 >= Mb/2 (h = 0) or n2 < Mb/2 (h = 1),
       // at window position n1 + Ma ((n2 + Mb/2) mod Mb) (reversed for line b')
       const bool rv = part && MIR;
-      const unsigned lane = obase + (unsigned)((rv ? (Ma - 1 - n1) : n1) * dps4);
+      const unsigned lane = obase + off_dst(rv ? (Ma - 1 - n1) : n1);
 #pragma unroll
       for (int n2 = 0; n2 < Mb; ++n2) {
         const float y = fmaf(sg, part ? v[n2].y : v[n2].x, lds[pb + lidx(1 - h, n2, n1)]);
         const int k = (n2 + Mb / 2) % Mb;
         const bool mine = (n2 >= Mb / 2) == (h == 0);
-        buf_st(dst, mine ? lane : kOOB, y, (rv ? Ma * (Mb - 1 - k) : Ma * k) * dps4);
+        buf_st(dd, mine ? lane : kOOB, y, (int)off_dst(rv ? Ma * (Mb - 1 - k) : Ma * k));
       }
     } else if constexpr (fast && IO == kIoWinFull) {
       // all P positions: n = m + h M (reversed, P - 1 - n, for line b')
@@ -631,30 +670,48 @@ constexpr bool staged() {
 // the pass reads half-turned frames through a different support (first shear
 // and column shear of a rotation), those frames are skipped here and handled
 // by line_pass_flipped_kernel.
-template <int M, int KIND, int G, int IO, bool MIR>
+//
+// With p.frame_group = g > 1 the blocks of g consecutive frames are
+// interleaved (frame fastest, then block of the frame; the last group may
+// hold fewer frames), so that blocks running side by side touch the same
+// lines of neighbouring frames: in a tile-major stack those are adjacent
+// 64-byte pieces of one run.
+template <int M, int KIND, int G, int IO, bool MIR, int TM>
 __global__ void __launch_bounds__(G * Shape<M>::JOB)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND>(), waves_per_eu<M, KIND>())))
 line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
   const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  const unsigned f = lb / (unsigned)p.blocks_per_frame;
-  const unsigned jb = lb - f * (unsigned)p.blocks_per_frame;
+  const unsigned bpf = (unsigned)p.blocks_per_frame;
+  unsigned f, jb;
+  if (p.frame_group > 1) {
+    const unsigned fg = (unsigned)p.frame_group;
+    const unsigned grp = lb / (fg * bpf);
+    const unsigned rem = lb - grp * (fg * bpf);
+    const unsigned f0 = grp * fg;
+    const unsigned cnt = min(fg, (unsigned)p.n_frames - f0);
+    jb = rem / cnt;
+    f = f0 + (rem - jb * cnt);
+  } else {
+    f = lb / bpf;
+    jb = lb - f * bpf;
+  }
   if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
     return;   // whole block leaves together, before any barrier
-  process_block<M, KIND, G, IO, MIR, staged<KIND, IO>()>(p, f, jb);
+  process_block<M, KIND, G, IO, MIR, staged<KIND, IO>(), TM>(p, f, jb);
 }
 
 // General path for the half-turned frames listed in p.flip_list (count in
 // p.flip_count): a fixed grid walks the (frame, block) pairs.
-template <int M, int KIND, int G, bool MIR>
+template <int M, int KIND, int G, bool MIR, int TM>
 __global__ void __launch_bounds__(G * Shape<M>::JOB, (waves_per_eu<M, KIND>()))
 line_pass_flipped_kernel(const LinePass p) {
   const unsigned bpf = (unsigned)p.blocks_per_frame;
   const unsigned work = (unsigned)(*p.flip_count) * bpf;
   for (unsigned w = blockIdx.x; w < work; w += gridDim.x) {
     const unsigned f = (unsigned)p.flip_list[w / bpf];
-    process_block<M, KIND, G, kIoGeneric, MIR>(p, f, w % bpf);
+    process_block<M, KIND, G, kIoGeneric, MIR, false, TM>(p, f, w % bpf);
     __syncthreads();
   }
 }
@@ -682,7 +739,7 @@ constexpr int row_jobs_per_block() {
   return 64 / Shape<M>::JOB > 0 ? 64 / Shape<M>::JOB : 1;
 }
 
-template <int M, int KIND, int G, int IO, bool MIR>
+template <int M, int KIND, int G, int IO, bool MIR, int TM = 0>
 static hipError_t launch_g(LinePass p, hipStream_t st) {
   using S = Shape<M>;
   static_assert(G * S::JOB <= 1024, "block too large");
@@ -690,20 +747,23 @@ static hipError_t launch_g(LinePass p, hipStream_t st) {
   p.blocks_per_frame = (p.n_jobs + G - 1) / G;
   const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const bool flipped = IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse);
+  if ((TM & 2) && flipped) return hipErrorInvalidValue;   // the general path stores frame-major only
   const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR>,
+  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR, TM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st, p);
+  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR, TM>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st,
+                     p);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || IO == kIoGeneric || p.flip == nullptr || !(p.flip_in_off || p.flip_src_reverse))
-    return e;
+  if (e != hipSuccess || !flipped) return e;
   // half-turned frames: general path over the device-side list
+  constexpr int TMF = TM & 1;
   const size_t lds_flip = (size_t)lds_floats<M, KIND, G, false>() * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, MIR>,
+  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, MIR, TMF>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_flip);
   const long long fb = std::min<long long>(blocks, 2048);
-  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR>), dim3((unsigned)fb), dim3(G * S::JOB), lds_flip, st,
-                     p);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR, TMF>), dim3((unsigned)fb), dim3(G * S::JOB), lds_flip,
+                     st, p);
   return hipGetLastError();
 }
 
@@ -751,8 +811,34 @@ constexpr int col_jobs_alt() {
   return M == 256 ? 8 : M == 512 ? 16 : M == 1024 ? 4 : M == 2048 ? 4 : 0;
 }
 
+// Tile-major passes of the ADI reduction (M >= 1024, cube launches): the
+// shift row pass (in place), the first and last rotation shears (source,
+// destination) and the shift column pass (destination).
+template <int M>
+static hipError_t launch_tile_major(const LinePass& p, int kind, int variant, hipStream_t st) {
+  if constexpr (M >= 1024) {
+    const int tm = (p.src_tm ? 1 : 0) | (p.dst_tm ? 2 : 0);
+    const int io = io_kind(p);
+    if (p.n_cubes < 1 || (long long)M * 4 * p.cubes[0].tm_T > 0x7fffffffLL) return hipErrorInvalidValue;
+    for (int i = 1; i < p.n_cubes; ++i)
+      if ((long long)M * 4 * p.cubes[i].tm_T > 0x7fffffffLL) return hipErrorInvalidValue;
+    constexpr int GR = row_jobs_per_block<M>();
+    if (kind == kRowPass) {
+      if (tm == 3 && !p.mirror && io == kIoWinWin) return launch_g<M, kRowPass, GR, kIoWinWin, false, 3>(p, st);
+      if (tm == 1 && p.mirror && io == kIoWinFull) return launch_g<M, kRowPass, GR, kIoWinFull, true, 1>(p, st);
+      if (tm == 2 && p.mirror && io == kIoFullWin) return launch_g<M, kRowPass, GR, kIoFullWin, true, 2>(p, st);
+    } else if (GRAPHIC_COL_STAGED && lanes_on_jobs<kColPass>() && tm == 2 && !p.mirror && io == kIoWinWin) {
+      constexpr int GA = col_jobs_alt<M>();
+      if (variant == 1 && GA > 0) return launch_g<M, kColPass, (GA > 0 ? GA : 1), kIoWinWin, false, 2>(p, st);
+      return launch_g<M, kColPass, col_jobs_per_block<M>(), kIoWinWin, false, 2>(p, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int M>
 static hipError_t launch_m(const LinePass& p, int kind, int variant, hipStream_t st) {
+  if (p.src_tm || p.dst_tm) return launch_tile_major<M>(p, kind, variant, st);
   if (kind == kRowPass) return launch_io<M, kRowPass, row_jobs_per_block<M>()>(p, st);
   constexpr int GA = col_jobs_alt<M>();
   if constexpr (GA > 0 && GRAPHIC_COL_STAGED && lanes_on_jobs<kColPass>()) {

@@ -283,6 +283,46 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   }
 }
 
+// The same on a tile-major stack: the block's 16 pixels over all T frames
+// are one run of 64 T bytes, and thread (px, g) finds frame g + 64 i of its
+// pixel at byte ((g + 64 i) * 16 + px) * 4 of the run, so each load of a wave
+// reads 256 contiguous bytes and the block streams its run once.  Offsets
+// past the run (frames >= T) are sent beyond the descriptor's extent.
+template <int VPT>
+__global__ void __launch_bounds__(16 * kGroups) median_tm_kernel(const float* __restrict__ stack, long long T,
+                                                                 long long npix, float* __restrict__ out,
+                                                                 float* resid) {
+  constexpr int kPix = 16;
+  extern __shared__ unsigned hist[];
+  __shared__ SelShared<kPix> sh;
+  const Tile<kPix> t(T, npix);
+  const unsigned run = (unsigned)(t.Ti * kPix * 4);
+  const unsigned voff = (unsigned)(t.g * kPix + t.px) * 4u;
+  unsigned key[VPT];
+  {
+    const __amdgpu_buffer_rsrc_t r = frames_rsrc(stack + t.pix0 * T, run);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const bool valid = t.g + kGroups * i < t.Ti;
+      const float v = __int_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(r, (int)(valid ? voff + (unsigned)(i * kGroups * kPix * 4) : 0x80000000u), 0, 0));
+      key[i] = valid ? key_of(v) : 0xFFFFFFFFu;
+    }
+  }
+  select_median<VPT, kPix>(t, key, ~0ull, (unsigned)T, hist, sh);
+  const float med = sh.med[t.px];
+  if (t.g == 0) out[t.pix] = med;
+  if (resid != nullptr) {
+    const __amdgpu_buffer_rsrc_t r = frames_rsrc(resid + t.pix0 * T, run);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const bool valid = t.g + kGroups * i < t.Ti;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), r,
+                                            (int)(valid ? voff + (unsigned)(i * kGroups * kPix * 4) : 0x80000000u), 0, 0);
+    }
+  }
+}
+
 // Per-frame medians over selected frames: for every frame f, the median of
 // the frames whose bit is set in row f of the selection (sel[f][g] bit i:
 // frame g + 64 i), written to psf[f] (nullable) and subtracted from frame f
@@ -475,6 +515,31 @@ hipError_t launch_median_nan(const float* stack, long long T, long long npix, fl
   GRAPHIC_NAN_CASE(32)
   GRAPHIC_NAN_CASE(64)
 #undef GRAPHIC_NAN_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_median_tile_major(const float* stack, long long T, long long npix, float* out, float* resid,
+                                    hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  if (npix % 16 != 0 || T > 4096) return hipErrorInvalidValue;
+  const long long vpt = (T + kGroups - 1) / kGroups;
+  const unsigned blocks = (unsigned)(npix / 16);
+  const size_t lds = (size_t)16 * 4 * kHistWords * sizeof(unsigned);
+#define GRAPHIC_TM_CASE(V)                                                                                  \
+  if (vpt <= V) {                                                                                          \
+    hipFuncSetAttribute((const void*)median_tm_kernel<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipLaunchKernelGGL((median_tm_kernel<V>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T, npix, out,  \
+                       resid);                                                                             \
+    return hipGetLastError();                                                                              \
+  }
+  GRAPHIC_TM_CASE(1)
+  GRAPHIC_TM_CASE(2)
+  GRAPHIC_TM_CASE(4)
+  GRAPHIC_TM_CASE(8)
+  GRAPHIC_TM_CASE(16)
+  GRAPHIC_TM_CASE(32)
+  GRAPHIC_TM_CASE(64)
+#undef GRAPHIC_TM_CASE
   return hipErrorInvalidValue;
 }
 
