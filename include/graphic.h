@@ -355,7 +355,9 @@ void graphic_graph_destroy(graphic_graph graph);
  * graphic_autotune times the library's alternative launch shapes for a
  * geometry on the caller's device -- the tile width (jobs per block) of the
  * column passes for both line pairings, and the pixel tile (16 or 8) of the
- * median for this frame count -- and keeps the fastest in the context; later
+ * median for this frame count, in the frame-major layout and, for the sizes
+ * whose ADI workspace stack is tile-major (P = 2N, N >= 1024), in that
+ * layout too -- and keeps the fastest in the context; later
  * calls with that geometry use them.  Every variant computes bit-identical
  * results.  It overwrites `ws` with synthetic frames and synchronises
  * `stream`.  Each kernel is timed at the size of one launch of the pipeline
@@ -368,7 +370,8 @@ void graphic_graph_destroy(graphic_graph graph);
  * GRAPHIC_ERR_WORKSPACE for a null or misaligned `ws`, GRAPHIC_ERR_HIP.
  *
  * graphic_tuning_export writes the tuned choices as text (one "col M pairing
- * variant" or "med class variant" line each) into buf (with its NUL; the
+ * variant", "med class variant" or "tmm class variant" line each, class =
+ * ceil(log2(ceil(T / 64)))) into buf (with its NUL; the
  * length needed, NUL included, goes to *needed; a short buffer gets a
  * truncated copy and GRAPHIC_ERR_ARG); graphic_tuning_import reads such text
  * back (all or nothing: a malformed line leaves the context unchanged and

@@ -71,9 +71,11 @@ struct graphic_ctx_s {
   // tuned launch variants (-1: not tuned, the default variant 0 runs)
   int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass
   int med_var[8];                         // [log2 of the median's values per thread]
+  int tmm_var[8];                         // the same for the tile-major median
   graphic_ctx_s() {
     for (auto& a : col_var) a[0] = a[1] = -1;
     for (int& v : med_var) v = -1;
+    for (int& v : tmm_var) v = -1;
   }
 };
 
@@ -224,6 +226,12 @@ int median_class(long long T) { return ilog2((int)((T + 63) / 64)) & 7; }
 int median_variant(graphic_ctx ctx, long long T) {
   const int v = ctx->med_var[median_class(T)];
   return v < 0 ? 0 : v;
+}
+
+// Tile-major median: 8-pixel tiles (two blocks per compute unit) unless tuned.
+int tm_median_variant(graphic_ctx ctx, long long T) {
+  const int v = ctx->tmm_var[median_class(T)];
+  return v >= 0 ? v : 1;
 }
 
 graphic_status run_pass(graphic_ctx ctx, const LinePass& p, int kind, const char* family, hipStream_t st) {
@@ -436,7 +444,7 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
 graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, float* resid,
                          hipStream_t st, bool tm = false) {
   Timer t(ctx, st, "median");
-  hipError_t e = tm ? launch_median_tile_major(stack, T, (long long)N * N, out, resid, st)
+  hipError_t e = tm ? launch_median_tile_major(stack, T, (long long)N * N, out, resid, tm_median_variant(ctx, T), st)
                     : launch_median(stack, T, (long long)N * N, out, resid, median_variant(ctx, T), st);
   t.done();
   return hip_ok(e);
@@ -1148,6 +1156,21 @@ graphic_status graphic_autotune(graphic_ctx ctx, const graphic_geom* geom, void*
     }
     if (!ok) return GRAPHIC_ERR_HIP;
     ctx->med_var[median_class(T)] = pick;
+    // the tile-major median of the large canonical sizes, the same way
+    if (P == 2 * N && N >= 1024) {
+      for (int v = 0; v < 2 && ok; ++v) {
+        const double ms = time_launches(st, 2, [&] {
+          hipError_t e = launch_median_tile_major(buf, T, npix, out, buf, v, st);
+          return e != hipSuccess ? e : launch_median_tile_major(buf, T, npix, out, nullptr, v, st);
+        }, &ok);
+        if (ok && (v == 0 || ms < best)) {
+          best = ms;
+          pick = v;
+        }
+      }
+      if (!ok) return GRAPHIC_ERR_HIP;
+      ctx->tmm_var[median_class(T)] = pick;
+    }
   }
   return GRAPHIC_OK;
 }
@@ -1161,6 +1184,8 @@ graphic_status graphic_tuning_export(graphic_ctx ctx, char* buf, size_t buf_len,
         t += "col " + std::to_string(1 << l) + " " + std::to_string(m) + " " + std::to_string(ctx->col_var[l][m]) + "\n";
   for (int c = 0; c < 8; ++c)
     if (ctx->med_var[c] >= 0) t += "med " + std::to_string(c) + " " + std::to_string(ctx->med_var[c]) + "\n";
+  for (int c = 0; c < 8; ++c)
+    if (ctx->tmm_var[c] >= 0) t += "tmm " + std::to_string(c) + " " + std::to_string(ctx->tmm_var[c]) + "\n";
   if (needed) *needed = t.size() + 1;
   if (buf && buf_len > 0) {
     const size_t n = std::min(buf_len - 1, t.size());
@@ -1173,9 +1198,10 @@ graphic_status graphic_tuning_export(graphic_ctx ctx, char* buf, size_t buf_len,
 
 graphic_status graphic_tuning_import(graphic_ctx ctx, const char* text) {
   if (!ctx || !text) return GRAPHIC_ERR_ARG;
-  int col[16][2], med[8];
+  int col[16][2], med[8], tmm[8];
   std::memcpy(col, ctx->col_var, sizeof(col));
   std::memcpy(med, ctx->med_var, sizeof(med));
+  std::memcpy(tmm, ctx->tmm_var, sizeof(tmm));
   const char* q = text;
   while (*q) {
     while (*q == '\n' || *q == ' ') ++q;
@@ -1185,9 +1211,10 @@ graphic_status graphic_tuning_import(graphic_ctx ctx, const char* text) {
     if (std::sscanf(q, "%3s %d %d %d%n", kind, &a, &b, &v, &used) == 4 && std::strcmp(kind, "col") == 0) {
       if (a < 8 || a > 2048 || (a & (a - 1)) || (b != 0 && b != 1) || v < 0 || v > 1) return GRAPHIC_ERR_ARG;
       col[ilog2(a)][b] = v;
-    } else if (std::sscanf(q, "%3s %d %d%n", kind, &a, &v, &used) == 3 && std::strcmp(kind, "med") == 0) {
+    } else if (std::sscanf(q, "%3s %d %d%n", kind, &a, &v, &used) == 3 &&
+               (std::strcmp(kind, "med") == 0 || std::strcmp(kind, "tmm") == 0)) {
       if (a < 0 || a > 7 || v < 0 || v > 1) return GRAPHIC_ERR_ARG;
-      med[a] = v;
+      (kind[0] == 'm' ? med : tmm)[a] = v;
     } else {
       return GRAPHIC_ERR_ARG;
     }
@@ -1199,6 +1226,7 @@ graphic_status graphic_tuning_import(graphic_ctx ctx, const char* text) {
   }
   std::memcpy(ctx->col_var, col, sizeof(col));
   std::memcpy(ctx->med_var, med, sizeof(med));
+  std::memcpy(ctx->tmm_var, tmm, sizeof(tmm));
   return GRAPHIC_OK;
 }
 

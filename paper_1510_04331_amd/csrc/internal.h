@@ -117,9 +117,9 @@ hipError_t launch_flip_list(const int* flip, long long f0, long long n, int* lis
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid,
                          int variant, hipStream_t s);
 // The same on a tile-major stack (npix a multiple of 16; resid, if non-null,
-// is tile-major too and may be stack).
+// is tile-major too and may be stack); variant as above.
 hipError_t launch_median_tile_major(const float* stack, long long T, long long npix, float* out, float* resid,
-                                    hipStream_t s);
+                                    int variant, hipStream_t s);
 
 // Frame selection of the per-frame PSF (sel: [T][64] bit rows, counts: [T]).
 hipError_t launch_select_frames(const double* times, const double* parang, long long T, double t_max,

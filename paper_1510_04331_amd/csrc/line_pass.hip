@@ -127,6 +127,10 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 #ifndef GRAPHIC_COL_DB_2048
 #define GRAPHIC_COL_DB_2048 0
 #endif
+// Occupancy target (waves per SIMD) of the same-pair row pass at M = 1024.
+#ifndef GRAPHIC_ROW_W_1024
+#define GRAPHIC_ROW_W_1024 3
+#endif
 #ifndef GRAPHIC_COL_WAVE_LAYOUT
 #define GRAPHIC_COL_WAVE_LAYOUT 0
 #endif
@@ -152,7 +156,7 @@ constexpr bool col_db() {
           : M == 2048 ? GRAPHIC_COL_DB_2048 : 1);
 }
 
-template <int M, int KIND>
+template <int M, int KIND, bool MIR = false>
 constexpr int waves_per_eu() {
   if (KIND == kColPass && lanes_on_jobs<KIND>()) {
     if (M == 256) return GRAPHIC_COL_W_256;
@@ -160,7 +164,8 @@ constexpr int waves_per_eu() {
     if (M == 1024) return GRAPHIC_COL_W_1024;
     if (M == 2048) return GRAPHIC_COL_W_2048;
   }
-  return M <= 256 ? 4 : (M == 1024 ? 3 : 2);
+  // rows of M = 1024: the mirror-paired shears fit 4 waves without spilling
+  return M <= 256 ? 4 : (M == 1024 ? (MIR ? 4 : GRAPHIC_ROW_W_1024) : 2);
 }
 
 typedef int v2i __attribute__((ext_vector_type(2)));
@@ -678,7 +683,7 @@ constexpr bool staged() {
 // 64-byte pieces of one run.
 template <int M, int KIND, int G, int IO, bool MIR, int TM>
 __global__ void __launch_bounds__(G * Shape<M>::JOB)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND>(), waves_per_eu<M, KIND>())))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND, MIR>(), waves_per_eu<M, KIND, MIR>())))
 line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;

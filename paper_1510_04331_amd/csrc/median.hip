@@ -283,43 +283,43 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
   }
 }
 
-// The same on a tile-major stack: the block's 16 pixels over all T frames
-// are one run of 64 T bytes, and thread (px, g) finds frame g + 64 i of its
-// pixel at byte ((g + 64 i) * 16 + px) * 4 of the run, so each load of a wave
-// reads 256 contiguous bytes and the block streams its run once.  Offsets
-// past the run (frames >= T) are sent beyond the descriptor's extent.
-template <int VPT>
-__global__ void __launch_bounds__(16 * kGroups) median_tm_kernel(const float* __restrict__ stack, long long T,
-                                                                 long long npix, float* __restrict__ out,
-                                                                 float* resid) {
-  constexpr int kPix = 16;
+// The same on a tile-major stack.  The block's kPix pixels (16, or 8 = one
+// half of a 16-pixel run) over all T frames lie in one run of 64 T bytes, and
+// thread (px, g) finds frame g + 64 i of its pixel at byte
+// ((g + 64 i) * 16 + px0 + px) * 4 of the run (px0: 0, or 8 for the second
+// half), so each load of a wave reads 64 / kPix frames of the tile from one
+// contiguous stretch.  Frame group i has its own wave-uniform descriptor
+// whose extent ends with frame T - 1, so frames past T read 0 and their
+// stores are dropped.  With kPix = 8, two blocks fit a compute unit.
+template <int VPT, int kPix>
+__global__ void __launch_bounds__(kPix * kGroups) median_tm_kernel(const float* __restrict__ stack, long long T,
+                                                                   long long npix, float* __restrict__ out,
+                                                                   float* resid) {
+  static_assert(kTilePix % kPix == 0, "a tile is a whole run or a part of one");
   extern __shared__ unsigned hist[];
   __shared__ SelShared<kPix> sh;
   const Tile<kPix> t(T, npix);
-  const unsigned run = (unsigned)(t.Ti * kPix * 4);
-  const unsigned voff = (unsigned)(t.g * kPix + t.px) * 4u;
+  const long long run0 = (t.pix0 / kTilePix) * T * kTilePix;         // float index of the run
+  const unsigned voff = (unsigned)(t.g * kTilePix + (int)(t.pix0 % kTilePix) + t.px) * 4u;
+  constexpr int kGroupFloats = kGroups * kTilePix;                   // 64 frames of the run
+  auto group_rsrc = [&](const float* base, int i) {
+    const long long left = (T - (long long)kGroups * i) * kTilePix * 4;
+    return frames_rsrc(base + run0 + (long long)i * kGroupFloats, left > 0 ? (unsigned)left : 0u);
+  };
   unsigned key[VPT];
-  {
-    const __amdgpu_buffer_rsrc_t r = frames_rsrc(stack + t.pix0 * T, run);
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-      const bool valid = t.g + kGroups * i < t.Ti;
-      const float v = __int_as_float(
-          __builtin_amdgcn_raw_buffer_load_b32(r, (int)(valid ? voff + (unsigned)(i * kGroups * kPix * 4) : 0x80000000u), 0, 0));
-      key[i] = valid ? key_of(v) : 0xFFFFFFFFu;
-    }
+  for (int i = 0; i < VPT; ++i) {
+    const float v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(group_rsrc(stack, i), (int)voff, 0, 0));
+    key[i] = t.g + kGroups * i < t.Ti ? key_of(v) : 0xFFFFFFFFu;
   }
   select_median<VPT, kPix>(t, key, ~0ull, (unsigned)T, hist, sh);
   const float med = sh.med[t.px];
   if (t.g == 0) out[t.pix] = med;
   if (resid != nullptr) {
-    const __amdgpu_buffer_rsrc_t r = frames_rsrc(resid + t.pix0 * T, run);
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-      const bool valid = t.g + kGroups * i < t.Ti;
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), r,
-                                            (int)(valid ? voff + (unsigned)(i * kGroups * kPix * 4) : 0x80000000u), 0, 0);
-    }
+    for (int i = 0; i < VPT; ++i)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), group_rsrc(resid, i), (int)voff,
+                                            0, 0);
   }
 }
 
@@ -518,18 +518,18 @@ hipError_t launch_median_nan(const float* stack, long long T, long long npix, fl
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_median_tile_major(const float* stack, long long T, long long npix, float* out, float* resid,
-                                    hipStream_t s) {
-  if (T <= 0 || npix <= 0) return hipSuccess;
-  if (npix % 16 != 0 || T > 4096) return hipErrorInvalidValue;
+template <int PIX>
+static hipError_t launch_median_tm_pix(const float* stack, long long T, long long npix, float* out, float* resid,
+                                       hipStream_t s) {
   const long long vpt = (T + kGroups - 1) / kGroups;
-  const unsigned blocks = (unsigned)(npix / 16);
-  const size_t lds = (size_t)16 * 4 * kHistWords * sizeof(unsigned);
+  const unsigned blocks = (unsigned)(npix / PIX);
+  const size_t lds = (size_t)PIX * (64 / PIX) * kHistWords * sizeof(unsigned);
 #define GRAPHIC_TM_CASE(V)                                                                                  \
   if (vpt <= V) {                                                                                          \
-    hipFuncSetAttribute((const void*)median_tm_kernel<V>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    hipLaunchKernelGGL((median_tm_kernel<V>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T, npix, out,  \
-                       resid);                                                                             \
+    hipFuncSetAttribute((const void*)median_tm_kernel<V, PIX>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                        (int)lds);                                                                         \
+    hipLaunchKernelGGL((median_tm_kernel<V, PIX>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, T, npix, \
+                       out, resid);                                                                        \
     return hipGetLastError();                                                                              \
   }
   GRAPHIC_TM_CASE(1)
@@ -541,6 +541,14 @@ hipError_t launch_median_tile_major(const float* stack, long long T, long long n
   GRAPHIC_TM_CASE(64)
 #undef GRAPHIC_TM_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_median_tile_major(const float* stack, long long T, long long npix, float* out, float* resid,
+                                    int variant, hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  if (npix % kTilePix != 0 || T > 4096) return hipErrorInvalidValue;
+  return variant == 1 ? launch_median_tm_pix<8>(stack, T, npix, out, resid, s)
+                      : launch_median_tm_pix<16>(stack, T, npix, out, resid, s);
 }
 
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid, int variant,

@@ -98,3 +98,28 @@ def test_tile_major_against_oracle(torch_dev):
     scale = np.linalg.norm(ref["psf"])
     assert np.linalg.norm(psf.cpu().numpy() - ref["psf"]) / scale <= REL_L2
     assert np.linalg.norm(fin.cpu().numpy() - ref["final"]) / scale <= REL_L2
+
+
+def test_tile_major_variants_bit_identical(torch_dev):
+    """Both tile widths of the staged column pass and both pixel tiles of the
+    tile-major median give the frame-major result; the autotuner picks among
+    them and reports its choice for the tile-major median."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("tile-major variants T=70 N=1024", flush=True)
+    T, N = 70, 1024
+    q = _params(N, T, 4, True)
+    cube = synth.render_device(q, dev)
+    ref, _ = G.adi_reduce(cube, q.dx, q.dy, q.parang, residuals=True)
+    ref = ref.cpu().numpy().tobytes()
+    cls = int(np.ceil(np.log2(max(1, -(-T // 64)))))
+    before = G.tuning_export()
+    try:
+        for v in (0, 1):
+            G.tuning_import("col %d 0 %d\ncol %d 1 %d\ntmm %d %d\n" % (N, v, N, v, cls, v))
+            assert G.adi_reduce(cube, q.dx, q.dy, q.parang).cpu().numpy().tobytes() == ref
+        text = G.autotune(T, N)
+        assert ("tmm %d" % cls) in text
+        assert G.adi_reduce(cube, q.dx, q.dy, q.parang).cpu().numpy().tobytes() == ref
+    finally:
+        G.tuning_import(before)

@@ -49,7 +49,7 @@ def test_variants_bit_identical(torch_dev, T, N):
 def test_tuning_import_rejects_bad_text(torch_dev):
     import paper_1510_04331_amd as G
     before = G.tuning_export()
-    for bad in ("col 1000 0 1\n", "col 512 2 0\n", "med 9 0\n", "col 512 0 3\n", "foo 1 2 3\n", "col 512 0 1 x\n"):
+    for bad in ("col 1000 0 1\n", "col 512 2 0\n", "med 9 0\n", "tmm 8 1\n", "tmm 3 2\n", "col 512 0 3\n", "foo 1 2 3\n", "col 512 0 1 x\n"):
         with pytest.raises(G.GraphicError):
             G.tuning_import(bad)
     assert G.tuning_export() == before
