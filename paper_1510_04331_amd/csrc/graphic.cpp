@@ -36,7 +36,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxT_Median = 4096;
 constexpr int kMaxT_Window = 2048;      // the per-frame median keeps a median per held frame in registers
-constexpr size_t kDefaultChunkBytes = size_t(1) << 30;   // rotation scratch per chunk
+constexpr size_t kDefaultChunkBytes = size_t(4) << 30;   // rotation scratch per chunk (fewer, fuller launches)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 

@@ -2,7 +2,7 @@
 bench.py times, on sampled outputs the oracle computes one by one.
 
 * SPHERE-like cube, 4096 frames of 1024 x 1024 (padded to 2048): the shift
-  (two passes over the whole cube), the rotation (chunks of 128 frames) and
+  (two passes over the whole cube), the rotation (chunks of 512 frames) and
   the exact median are checked on sampled frames and pixels; the full ADI
   reduction is checked through a property that holds at any size (identical
   frames leave exactly zero residuals and a zero final image).
@@ -53,7 +53,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-SAMPLE_FRAMES = (0, 127, 128, 2047, 4095)   # first / last frame of rotation chunks, middle, end
+SAMPLE_FRAMES = (0, 511, 512, 2047, 4095)   # first / last frame of rotation chunks, middle, end
 
 
 def test_shift_full_size(torch_dev, sphere):

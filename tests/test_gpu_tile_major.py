@@ -44,7 +44,7 @@ def _params(N, T, seed, wide):
 def _small_ws(torch, dev, bytes_default, N, F, chunk):
     """A workspace that leaves room for about `chunk` frames per rotation chunk."""
     per_frame = N * 2 * N * 4
-    default_cf = min(F, (1 << 30) // per_frame)
+    default_cf = min(F, (4 << 30) // per_frame)
     return torch.empty(bytes_default - (default_cf - chunk) * per_frame, dtype=torch.uint8, device=dev)
 
 
