@@ -20,6 +20,10 @@ Two more workloads print their own JSON line:
         paper's frame selection, 1024 frames of 512^2
     python bench.py --workload register registration (centroid + Moffat fit)
         of 1024 frames of 512^2
+    python bench.py --workload quality  the image-quality test of Sect. 4:
+        256 frames of 1024^2 shifted by (3.5, 2.7) px and back and rotated by
+        11.3 deg and back, residual RMS in 2-px annuli; the third-order
+        spline curve of the paper (scipy, CPU, first frame) is reported beside
 """
 
 import argparse
@@ -332,6 +336,68 @@ def bench_register(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_quality(args):
+    """Image-quality test of Sect. 4 on SPHERE-like frames: one step is the
+    double shift and the double rotation of every frame plus the annular RMS
+    of both residual stacks."""
+    import numpy as np
+    import torch
+    import paper_1510_04331_amd as G
+    import synth
+    from scipy import ndimage
+    dev = torch.device("cuda:0")
+    T = min(args.frames, 256)
+    p = synth.make_params(3, T=T, N=args.size)
+    cube = synth.render_device(p, dev)
+    N = p.N
+    dx, dy = np.full(T, 3.5), np.full(T, 2.7)
+    ang = np.full(T, 11.3)
+    n_rings = int(N * 0.7072 // 2.0) + 1
+
+    def step():
+        s = G.shift(G.shift(cube, dx, dy), -dx, -dy)
+        rs, _ = G.annular_rms(s, cube, 2.0, n_rings)
+        del s
+        r = G.rotate(G.rotate(cube, ang), -ang)
+        rr, _ = G.annular_rms(r, cube, 2.0, n_rings)
+        return rs, rr
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rs, rr = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    base, _ = G.annular_rms(cube[:1], None, 2.0, n_rings)
+    f0 = cube[0].double().cpu().numpy()
+    peak = float(f0.max())
+    # the paper's comparison curve: third-order spline round trips of frame 0
+    spl_s = ndimage.shift(ndimage.shift(f0, (2.7, 3.5), order=3, mode="constant"), (-2.7, -3.5), order=3,
+                          mode="constant")
+    spl_r = ndimage.rotate(ndimage.rotate(f0, 11.3, reshape=False, order=3, mode="constant"), -11.3, reshape=False,
+                           order=3, mode="constant")
+    f0t = torch.from_numpy(f0.astype(np.float32)).to(dev)
+    ss, _ = G.annular_rms(torch.from_numpy(spl_s.astype(np.float32)).to(dev), f0t, 2.0, n_rings)
+    sr, _ = G.annular_rms(torch.from_numpy(spl_r.astype(np.float32)).to(dev), f0t, 2.0, n_rings)
+    radii = [r for r in (10, 25, 50, 100, 200, 400) if r // 2 < n_rings]
+    prof = lambda v: {str(r): float("%.3g" % (float(v[r // 2]) / peak)) for r in radii}
+    out = {"metric": "frames round-tripped/s (double shift + double rotation + annular RMS of both)",
+           "value": round(T / dt, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True, "dtype": "f32 (f64 sums)",
+           "data": "synthetic",
+           "config": {"workload": "%d SPHERE-like frames of %dx%d, shift (3.5, 2.7) px and back, rotation 11.3 deg "
+                                  "and back, RMS in 2-px annuli" % (T, N, N)},
+           "profile_radius_px_over_peak": {
+               "image": prof(base.cpu().numpy()[0]),
+               "fourier_shift_residual": prof(rs.cpu().numpy()[0]),
+               "spline_shift_residual": prof(ss.cpu().numpy()),
+               "fourier_rotation_residual": prof(rr.cpu().numpy()[0]),
+               "spline_rotation_residual": prof(sr.cpu().numpy())}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_served(args):
     import numpy as np
     import torch
@@ -395,7 +461,7 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register"), default="adi")
+    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register", "quality"), default="adi")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning (default launch shapes; keeps tuning launches out of profiles)")
     ap.add_argument("--requests", type=int, default=1000)
@@ -422,6 +488,8 @@ def main():
         return bench_window(args)
     if args.workload == "register":
         return bench_register(args)
+    if args.workload == "quality":
+        return bench_quality(args)
 
     cpu = None
     if not args.no_cpu_baseline:

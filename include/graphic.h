@@ -191,7 +191,8 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
  *               one of psf_cube and resid is given.
  *   ws        : graphic_workspace_size(GRAPHIC_OP_MEDIAN_WINDOW) bytes (the
  *               selection: T x 512 bytes plus T ints).
- * Cost: one select per frame over its selected frames, O(T^2 N^2).
+ * Cost: one sort of every pixel's T values, then per frame O(T / 64) work
+ * per pixel plus the frames that enter or leave the selection.
  */
 graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, const float* stack,
                                      const double* times, const double* parang_deg, double t_max,
@@ -291,6 +292,29 @@ graphic_status graphic_badpix_map(graphic_ctx ctx, int32_t n, const float* frame
 graphic_status graphic_badpix_fix(graphic_ctx ctx, const graphic_geom* geom, float* cube, const uint8_t* map,
                                   int32_t max_passes, int32_t* passes, void* ws, size_t ws_bytes,
                                   graphic_stream stream);
+
+/*
+ * Image-quality test (Sect. 4): the paper shifts an image by (3.5, 2.7) px
+ * and back, or rotates it by 11.3 deg and back, subtracts the original and
+ * plots the root mean square of the difference in concentric annuli.  The
+ * round trips are graphic_shift / graphic_rotate calls; this entry point
+ * measures the difference.
+ *
+ * graphic_annular_rms: for every frame t of the [T][N][N] float32 stack a
+ *   (geometry as graphic_geom, pad ignored; T <= 65535), the RMS of
+ *   a[t] - b[t] (b NULL: of a[t]; else the same shape as a) over each annulus
+ *   k = 0 .. n_rings - 1 of width `width` px around (cx, cy): the pixels
+ *   (x, y), x the column, with (k width)^2 <= (x - cx)^2 + (y - cy)^2 <
+ *   ((k + 1) width)^2, compared in float64 without a square root.  Sums are
+ *   float64.  rms [T][n_rings] float64 device memory (NaN for an annulus
+ *   with no pixel); counts [n_rings] int64 device memory (pixels per
+ *   annulus).  1 <= n_rings <= 4096; width, cx and cy finite, width > 0 and
+ *   (|cx| + |cy| + 2N) / width < 2^30.  The sums are float64 atomics, so
+ *   repeated calls agree to rounding, not bit for bit.
+ */
+graphic_status graphic_annular_rms(graphic_ctx ctx, const graphic_geom* geom, const float* a, const float* b,
+                                   double cx, double cy, double width, int32_t n_rings, double* rms, int64_t* counts,
+                                   graphic_stream stream);
 
 /*
  * Batched ADI reduction of cubes of uneven frame count and size (the

@@ -6,7 +6,7 @@ C ABI of include/graphic.h; this package only marshals torch tensors to it.
 
 from .ops import (shift, rotate, median, adi_reduce, adi_reduce_batch, workspace_size,  # noqa: F401
                   median_window, adi_reduce_window, alpha_min_deg, parallactic_angles, register,
-                  median_nan, mask_disk, subtract_nearest, badpix_map, badpix_fix,
+                  median_nan, mask_disk, subtract_nearest, badpix_map, badpix_fix, annular_rms,
                   batch_workspace_size, AdiGraph, autotune, tuning_export, tuning_import,
                   timing_enable, timing_read)
 from ._abi import LIB_PATH, GraphicError  # noqa: F401

@@ -21,7 +21,7 @@ EXPORTS = (
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
     "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_adi_reduce_window",
     "graphic_parallactic_angles", "graphic_register", "graphic_median_nan", "graphic_mask_disk",
-    "graphic_subtract_nearest", "graphic_badpix_map", "graphic_badpix_fix",
+    "graphic_subtract_nearest", "graphic_badpix_map", "graphic_badpix_fix", "graphic_annular_rms",
     "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
     "graphic_adi_graph_create", "graphic_graph_launch", "graphic_graph_destroy",
     "graphic_autotune", "graphic_tuning_export", "graphic_tuning_import",
@@ -107,6 +107,8 @@ def load():
     lib.graphic_badpix_map.restype = st
     lib.graphic_badpix_fix.argtypes = [vp, g, vp, vp, i32, ctypes.POINTER(i32), vp, sz, vp]
     lib.graphic_badpix_fix.restype = st
+    lib.graphic_annular_rms.argtypes = [vp, g, vp, vp, f64, f64, f64, i32, vp, vp, vp]
+    lib.graphic_annular_rms.restype = st
     cd = ctypes.POINTER(CubeDesc)
     lib.graphic_batch_workspace_size.argtypes = [vp, cd, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(sz)]
     lib.graphic_batch_workspace_size.restype = st

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgraphic.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["line_pass.hip", "median.hip", "aux_kernels.hip", "register.hip", "preprocess.hip", "graphic.cpp"]
+SOURCES = ["line_pass.hip", "median.hip", "aux_kernels.hip", "register.hip", "preprocess.hip", "quality.hip",
+           "graphic.cpp"]
 
 ARCH = os.environ.get("GRAPHIC_OFFLOAD_ARCH", "gfx950")
 

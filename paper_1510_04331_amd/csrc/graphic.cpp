@@ -296,14 +296,17 @@ graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it
       F += it[i0 + k].T;
     }
     c.n_frames = F;
+    // the column pass keeps frame-by-frame block order: its frame-major reads
+    // of 16-column strips then share 128-byte lines between neighbouring
+    // blocks, which matters more than the adjacency of its tile-major stores
     c.dst_tm = tm ? 1 : 0;
-    c.frame_group = tm ? ctx->frame_group : 0;
     graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
     if (s != GRAPHIC_OK) return s;
     LinePass r = c;
     r.src_ls = r.dst_ls = N;
     r.src_ps = r.dst_ps = 1;
     r.src_tm = r.dst_tm = tm ? 1 : 0;
+    r.frame_group = tm ? ctx->frame_group : 0;
     for (int k = 0; k < g; ++k)
       r.cubes[k] = CubeRef{it[i0 + k].out, it[i0 + k].out, it[i0 + k].dx, c.cubes[k].frame0, it[i0 + k].T};
     if ((s = run_pass(ctx, r, kRowPass, "shift_x", st)) != GRAPHIC_OK) return s;
@@ -564,6 +567,8 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
     // S_i = shift(cube_i): every cube of the class in the same launches
     if ((s = do_shift_batch(ctx, N, P, sh.data(), (int)sh.size(), st, tm)) != GRAPHIC_OK) return s;
     // PSF = median_i S_i; the median also rewrites the stack as S_i - PSF
+    // (cheaper than subtracting the PSF in the first shear's loads: that
+    // doubles the shear's reads, while the rewrite costs one streaming write)
     for (int i : c)
       if ((s = do_median(ctx, d[i].n_frames, N, stack[i], psf[i], stack[i], st, tm)) != GRAPHIC_OK) return s;
     // D_i = rotate(S_i - PSF, -parang_i), in place
@@ -975,6 +980,29 @@ graphic_status graphic_badpix_fix(graphic_ctx ctx, const graphic_geom* geom, flo
     return GRAPHIC_ERR_HIP;
   if (passes) *passes = done;
   return GRAPHIC_OK;
+}
+
+graphic_status graphic_annular_rms(graphic_ctx ctx, const graphic_geom* geom, const float* a, const float* b,
+                                   double cx, double cy, double width, int32_t n_rings, double* rms, int64_t* counts,
+                                   graphic_stream stream) {
+  graphic_status s = frames_args(ctx, geom, a);
+  if (s != GRAPHIC_OK) return s;
+  if (!rms || !counts || n_rings < 1 || n_rings > kMaxRings) return GRAPHIC_ERR_ARG;
+  if (!std::isfinite(width) || !std::isfinite(cx) || !std::isfinite(cy) || !(width > 0.0)) return GRAPHIC_ERR_ARG;
+  if ((std::fabs(cx) + std::fabs(cy) + 2.0 * geom->n) / width >= 1073741824.0) return GRAPHIC_ERR_ARG;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  const size_t frames_b = (size_t)T * N * N * sizeof(float);
+  const char* ra = reinterpret_cast<const char*>(rms);
+  const size_t rms_b = (size_t)T * n_rings * sizeof(double);
+  auto overlaps = [&](const void* x, size_t xb) {
+    const char* q = static_cast<const char*>(x);
+    return q < ra + rms_b && ra < q + xb;
+  };
+  if (overlaps(a, frames_b) || (b && overlaps(b, frames_b)) || overlaps(counts, (size_t)n_rings * sizeof(int64_t)))
+    return GRAPHIC_ERR_ARG;
+  return hip_ok(launch_annular_rms(a, b, T, N, cx, cy, width, n_rings, rms, reinterpret_cast<long long*>(counts),
+                                   static_cast<hipStream_t>(stream)));
 }
 
 graphic_status graphic_batch_workspace_size(graphic_ctx ctx, const graphic_cube_desc* descs, int n_cubes,

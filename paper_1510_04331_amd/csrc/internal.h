@@ -160,6 +160,14 @@ hipError_t launch_badpix_map(const float* frame, int n, double c_sigma, unsigned
 hipError_t launch_apply_map(float* cube, long long T, int n, const unsigned char* map, hipStream_t s);
 hipError_t launch_repair_pass(const float* src, float* dst, long long T, int n, int* flags, hipStream_t s);
 
+// Image-quality test (Sect. 4): RMS of a - b (b nullable) in n_rings annuli
+// of width `width` around (cx, cy), per frame of [T][N][N] stacks, into
+// rms[T][n_rings] (NaN: empty annulus) and counts[n_rings] (pixels per
+// annulus); n_rings <= kMaxRings, T <= 65535.
+constexpr int kMaxRings = 4096;
+hipError_t launch_annular_rms(const float* a, const float* b, long long T, int N, double cx, double cy, double width,
+                              int n_rings, double* rms, long long* counts, hipStream_t s);
+
 // n floats of seeded noise around a sky level (for timing runs on scratch).
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
 

@@ -326,35 +326,164 @@ __global__ void __launch_bounds__(kPix * kGroups) median_tm_kernel(const float* 
 // Per-frame medians over selected frames: for every frame f, the median of
 // the frames whose bit is set in row f of the selection (sel[f][g] bit i:
 // frame g + 64 i), written to psf[f] (nullable) and subtracted from frame f
-// into resid (nullable; in place allowed).  One block keeps its pixel tile's
-// whole stack in registers and runs the select once per frame.
-template <int VPT, bool BUF>
-__global__ void __launch_bounds__(16 * kGroups)
-median_window_kernel(const float* __restrict__ stack, long long T, long long npix,
-                     const unsigned long long* __restrict__ sel, const int* __restrict__ counts,
-                     float* __restrict__ psf, float* resid) {
-  constexpr int kPix = 16;
-  extern __shared__ unsigned hist[];
-  __shared__ SelShared<kPix> sh;
-  const Tile<kPix> t(T, npix);
-  unsigned key[VPT];
-  load_keys<VPT, kPix, BUF>(t, stack, npix, key);
-  float med_own[VPT];                                    // median of each of this thread's frames
+// into resid (nullable; in place allowed).
+//
+// A block owns PB pixels, one wave each.  The block first reads its pixels'
+// whole stack (coalesced over the pixels) into LDS; each wave then sorts its
+// pixel's keys once, by a bitonic network over (key, frame) pairs held as
+// element e = lane * VPT + r, and keeps the sorted keys and the sorted
+// position of every frame in LDS.  A bitmap over sorted positions marks the
+// selected frames: from one frame to the next only the frames that enter or
+// leave the selection flip their bit, so with sliding selections a frame
+// costs O(1) LDS updates.  Each lane counts the marked positions of its own
+// VPT-bit stretch, a wave prefix sum locates the lanes holding ranks
+// (K - 1) / 2 and K / 2 of the K selected keys, and those lanes find the bit
+// within their stretch.  The two keys give the median exactly as the
+// radix select does: (lo + hi) * 0.5 in float32.
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int mask) {
+  const int lo = __shfl_xor((int)(unsigned)v, mask);
+  const int hi = __shfl_xor((int)(unsigned)(v >> 32), mask);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Index of the j-th set bit (from 0) of m (j < popcount(m)).
+__device__ __forceinline__ int nth_set_bit(unsigned m, unsigned j) {
+  int r = 0;
 #pragma unroll
-  for (int i = 0; i < VPT; ++i) med_own[i] = 0.0f;
-#pragma unroll 1
-  for (int f = 0; f < t.Ti; ++f) {
-    const unsigned long long bits = sel[(size_t)f * kGroups + t.g];
-    select_median<VPT, kPix>(t, key, bits, (unsigned)counts[f], hist, sh);
-    const float m = sh.med[t.px];
-    if (t.g == 0 && t.pix_ok && psf != nullptr) psf[(size_t)f * npix + t.pix] = m;
-    if (t.g == (f & (kGroups - 1))) {
-#pragma unroll
-      for (int i = 0; i < VPT; ++i)
-        if (i == (f >> 6)) med_own[i] = m;
+  for (int step = 16; step >= 1; step >>= 1) {
+    const unsigned low = (unsigned)__popc(m & ((1u << step) - 1u));
+    if (j >= low) {
+      j -= low;
+      m >>= step;
+      r += step;
     }
   }
-  if (resid != nullptr) store_diff<VPT, kPix, BUF>(t, resid, npix, key, med_own);
+  return r;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int VPT, int PB>
+__global__ void __launch_bounds__(PB * 64)
+median_window_kernel(const float* __restrict__ stack, long long T, long long npix,
+                     const unsigned long long* __restrict__ sel, float* __restrict__ psf, float* resid) {
+  constexpr int TP = 64 * VPT;                          // padded frame count of one pixel
+  constexpr int kWords = TP / 32;                       // bitmap words of one pixel
+  static_assert(VPT >= 1 && VPT <= 32 && (VPT & (VPT - 1)) == 0, "VPT: power of two up to 32");
+  extern __shared__ unsigned s_dyn[];
+  unsigned* s_key = s_dyn;                                                       // [PB][TP]
+  unsigned short* s_pos = reinterpret_cast<unsigned short*>(s_key + PB * TP);    // [PB][TP]
+  unsigned* s_bits = reinterpret_cast<unsigned*>(s_pos + PB * TP);              // [PB][kWords]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int Ti = (int)T;
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const long long pix0 = (long long)tile * PB;
+
+  // 1. the tile's stack into LDS: thread (px, g) reads frames g + 64 i, so a
+  //    wave's load covers PB neighbouring pixels of 64 / PB frames
+  {
+    const int px = lane % PB, g = lane / PB + (64 / PB) * w;
+    const bool ok = pix0 + px < npix;
+#pragma unroll 4
+    for (int i = 0; i < VPT; ++i) {
+      const int f = g + 64 * i;
+      s_key[px * TP + f] = (ok && f < Ti) ? key_of(stack[(long long)f * npix + pix0 + px]) : 0xFFFFFFFFu;
+    }
+  }
+  __syncthreads();
+
+  // 2. wave w sorts pixel w: (key << 11 | frame), frames past T sort last
+  unsigned* key = s_key + w * TP;
+  unsigned short* pos = s_pos + w * TP;
+  unsigned* bits = s_bits + w * kWords;
+  {
+    unsigned long long v[VPT];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+      const int e = lane * VPT + r;
+      v[r] = ((unsigned long long)key[e] << 11) | (unsigned)e;
+    }
+#pragma unroll
+    for (int k = 2; k <= TP; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= VPT) {                                 // partner in lane ^ (j / VPT), same register
+          const bool upper = (lane & (j / VPT)) != 0;
+          const bool asc = ((lane * VPT) & k) == 0;
+#pragma unroll
+          for (int r = 0; r < VPT; ++r) {
+            const unsigned long long o = shfl_xor_u64(v[r], j / VPT);
+            v[r] = (asc != upper) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+          }
+        } else {                                        // partner in this lane
+#pragma unroll
+          for (int r = 0; r < VPT; ++r) {
+            if ((r & j) != 0) continue;
+            const bool asc = (((lane * VPT + r) & k) == 0);
+            const unsigned long long x = v[r], y = v[r | j];
+            const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+            v[r] = asc ? lo : hi;
+            v[r | j] = asc ? hi : lo;
+          }
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+      const int e = lane * VPT + r;
+      key[e] = (unsigned)(v[r] >> 11);
+      pos[(int)(v[r] & 0x7FFu)] = (unsigned short)e;
+    }
+    for (int i = lane; i < kWords; i += 64) bits[i] = 0u;
+    wave_sync();
+  }
+
+  // 3. frame loop: flip the bits of the frames that enter or leave the
+  //    selection, count per lane, locate ranks (K - 1) / 2 and K / 2
+  const long long pix = pix0 + w;
+  const bool pix_ok = pix < npix;
+  const int b0 = lane * VPT;
+  unsigned long long prev = 0ull;
+  unsigned long long cur = sel[lane];
+#pragma unroll 1
+  for (int f = 0; f < Ti; ++f) {
+    const unsigned long long nxt = f + 1 < Ti ? sel[(size_t)(f + 1) * kGroups + lane] : 0ull;
+    unsigned long long d = cur ^ prev;
+    prev = cur;
+    while (d != 0ull) {
+      const int i = __ffsll((long long)d) - 1;
+      d &= d - 1ull;
+      const int p = pos[lane + 64 * i];
+      atomicXor(&bits[p >> 5], 1u << (p & 31));
+    }
+    wave_sync();
+    const unsigned word = bits[b0 >> 5];
+    const unsigned m = VPT == 32 ? word : (word >> (b0 & 31)) & ((1u << (VPT & 31)) - 1u);
+    const unsigned cnt = (unsigned)__popc(m);
+    const unsigned incl = wave_incl_scan(cnt);
+    const unsigned K = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+    auto key_of_rank = [&](unsigned k) -> unsigned {
+      const int L = __ffsll((long long)__ballot(incl > k)) - 1;
+      const int at = b0 + nth_set_bit(m, k - (incl - cnt));
+      return key[__builtin_amdgcn_readlane(at, L)];
+    };
+    const unsigned klo = K == 0u ? 0u : (K - 1u) / 2u;
+    const float lo = val_of(key_of_rank(klo));
+    const float hi = K / 2u == klo ? lo : val_of(key_of_rank(K / 2u));
+    const float med = (lo + hi) * 0.5f;
+    if (lane == 0 && pix_ok) {
+      if (psf != nullptr) psf[(size_t)f * npix + pix] = med;
+      if (resid != nullptr) resid[(size_t)f * npix + pix] = val_of(key[pos[f]]) - med;
+    }
+    cur = nxt;
+    wave_sync();
+  }
 }
 
 // Per-pixel median ignoring NaN values (the master sky of Sect. 3.1: star
@@ -454,35 +583,29 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
   return hipGetLastError();
 }
 
+template <int V, int PB>
+static hipError_t launch_window_v(const float* stack, long long T, long long npix, const unsigned long long* sel,
+                                  float* psf, float* resid, hipStream_t s) {
+  constexpr int TP = 64 * V;
+  const size_t lds = (size_t)PB * TP * (sizeof(unsigned) + sizeof(unsigned short)) + (size_t)PB * (TP / 32) * 4;
+  const unsigned blocks = (unsigned)((npix + PB - 1) / PB);
+  hipFuncSetAttribute((const void*)median_window_kernel<V, PB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((median_window_kernel<V, PB>), dim3(blocks), dim3(PB * 64), lds, s, stack, T, npix, sel, psf,
+                     resid);
+  return hipGetLastError();
+}
+
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
                                 const int* counts, float* psf, float* resid, hipStream_t s) {
+  (void)counts;   // the selection bits carry the counts
   if (T <= 0 || npix <= 0) return hipSuccess;
   const long long vpt = (T + kGroups - 1) / kGroups;
-  const unsigned blocks = (unsigned)((npix + 15) / 16);
-  const bool buf = (long long)kGroups * npix * 4 < 0x7fffffffLL;
-  const size_t lds = (size_t)16 * 4 * kHistWords * sizeof(unsigned);
-#define GRAPHIC_WINDOW_CASE(V)                                                                             \
-  if (vpt <= V) {                                                                                         \
-    if (buf) {                                                                                            \
-      hipFuncSetAttribute((const void*)median_window_kernel<V, true>,                                     \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                          \
-      hipLaunchKernelGGL((median_window_kernel<V, true>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, \
-                         T, npix, sel, counts, psf, resid);                                               \
-    } else {                                                                                              \
-      hipFuncSetAttribute((const void*)median_window_kernel<V, false>,                                    \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                          \
-      hipLaunchKernelGGL((median_window_kernel<V, false>), dim3(blocks), dim3(16 * kGroups), lds, s,      \
-                         stack, T, npix, sel, counts, psf, resid);                                        \
-    }                                                                                                     \
-    return hipGetLastError();                                                                             \
-  }
-  GRAPHIC_WINDOW_CASE(1)
-  GRAPHIC_WINDOW_CASE(2)
-  GRAPHIC_WINDOW_CASE(4)
-  GRAPHIC_WINDOW_CASE(8)
-  GRAPHIC_WINDOW_CASE(16)
-  GRAPHIC_WINDOW_CASE(32)
-#undef GRAPHIC_WINDOW_CASE
+  if (vpt <= 1) return launch_window_v<1, 16>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 2) return launch_window_v<2, 16>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 4) return launch_window_v<4, 16>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 8) return launch_window_v<8, 16>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 16) return launch_window_v<16, 16>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 32) return launch_window_v<32, 8>(stack, T, npix, sel, psf, resid, s);
   return hipErrorInvalidValue;   // T > 2048: rejected on the host before launch
 }
 

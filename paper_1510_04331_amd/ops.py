@@ -322,6 +322,37 @@ def badpix_fix(cube, bad_map=None, max_passes=64):
     return passes.value
 
 
+def annular_rms(a, b=None, width=1.0, n_rings=None, centre=None):
+    """RMS of a - b (or of a) in annuli of `width` px around `centre` (x, y;
+    default (N/2, N/2)) for every frame of a [T, N, N] (or [N, N]) tensor,
+    the image-quality measure of Sect. 4.  Returns (rms [T, n_rings] or
+    [n_rings] float64, counts [n_rings] int64), both on the device; n_rings
+    defaults to the annuli that reach the frame corners."""
+    import math
+    import torch
+    single = a.dim() == 2
+    a3 = a.unsqueeze(0) if single else a
+    T, N = _check_cube(a3, "a")
+    b3 = None
+    if b is not None:
+        b3 = b.unsqueeze(0) if b.dim() == 2 else b
+        _check_cube(b3, "b")
+        if b3.shape != a3.shape or b3.device != a3.device:
+            raise ValueError("b must have the shape and device of a")
+    cx, cy = (N / 2.0, N / 2.0) if centre is None else (float(centre[0]), float(centre[1]))
+    if n_rings is None:
+        far = max(math.hypot(x - cx, y - cy) for x in (0, N - 1) for y in (0, N - 1))
+        n_rings = int(far // width) + 1
+    dev = a3.device
+    rms = torch.empty((T, int(n_rings)), dtype=torch.float64, device=dev)
+    counts = torch.empty(int(n_rings), dtype=torch.int64, device=dev)
+    g = _geom(T, N, 0)
+    _abi.check(_abi.load().graphic_annular_rms(context(dev.index or 0), ctypes.byref(g), _ptr(a3), _ptr(b3), cx, cy,
+                                               float(width), int(n_rings), _ptr(rms), _ptr(counts), _stream(dev)),
+               "graphic_annular_rms")
+    return (rms[0] if single else rms), counts
+
+
 def _batch_descs(cubes, dx, dy, parang, pad, psf, residuals):
     import torch
     n = len(cubes)

@@ -1,0 +1,98 @@
+"""GPU: the image-quality test of Sect. 4 against the oracle.
+
+The annular RMS has the oracle's pixel counts exactly and its float64 RMS to
+rounding (the GPU adds the squares in atomics' order).  The round trips of
+the paper (shift by (3.5, 2.7) px and back, rotation by 11.3 deg and back)
+meet the shift / rotation bar against the oracle's float64 round trips, and
+their residual profiles stay below those of third-order spline interpolation
+(scipy), as the paper finds."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import quality as Q
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+def _same_nan(a, b):
+    return np.array_equal(np.isnan(a), np.isnan(b))
+
+
+@pytest.mark.parametrize("N,T,width,centre,n_rings,with_b", [
+    (32, 1, 1.0, None, 30, False),
+    (33, 2, 1.0, None, 30, True),                 # odd size, centre between pixels
+    (128, 3, 2.5, (60.5, 70.25), 40, True),       # off-centre, fractional width
+    (256, 2, 7.0, None, 30, True),                # rings past the corners stay empty
+    (250, 2, 1.0, (0.0, 0.0), 400, False),        # centre on a corner pixel
+])
+def test_annular_rms_against_oracle(torch_dev, N, T, width, centre, n_rings, with_b):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("annular rms N=%d T=%d width=%g centre=%s" % (N, T, width, centre), flush=True)
+    rng = np.random.default_rng(N + T)
+    a = rng.normal(3.0, 2.0, (T, N, N)).astype(np.float32)
+    b = rng.normal(3.0, 2.0, (T, N, N)).astype(np.float32) if with_b else None
+    at = torch.from_numpy(a).to(dev)
+    bt = torch.from_numpy(b).to(dev) if with_b else None
+    rms, counts = G.annular_rms(at, bt, width, n_rings, centre)
+    cx, cy = (N / 2.0, N / 2.0) if centre is None else centre
+    ref, rc = Q.annular_rms(a, b, width, n_rings, cx, cy)
+    assert counts.cpu().numpy().tolist() == rc.tolist()
+    got = rms.cpu().numpy()
+    assert _same_nan(got, ref)
+    ok = ~np.isnan(ref)
+    assert np.all(np.abs(got[ok] - ref[ok]) <= 1e-12 * ref[ok])
+
+
+def test_annular_rms_single_frame_and_errors(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    img = torch.full((16, 16), 2.0, dtype=torch.float32, device=dev)
+    rms, counts = G.annular_rms(img, None, 1.0, 4)
+    assert rms.shape == (4,) and counts.cpu().tolist() == [1, 8, 16, 20]
+    assert np.allclose(rms.cpu().numpy(), 2.0, rtol=0, atol=0)
+    for bad in (dict(width=0.0), dict(width=float("nan")), dict(n_rings=0), dict(n_rings=5000)):
+        kw = dict(width=1.0, n_rings=4)
+        kw.update(bad)
+        with pytest.raises(G.GraphicError):
+            G.annular_rms(img, None, **kw)
+
+
+@pytest.mark.parametrize("kind", ["shift", "rotate"])
+def test_round_trip_profiles(torch_dev, kind):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("double %s of a 256^2 frame" % kind, flush=True)
+    p = synth.make_params(2, seed=synth.BASE_SEED + 400, T=1, N=256)
+    img = synth.render_host(p)                                   # [1, 256, 256] float32
+    it = torch.from_numpy(img).to(dev)
+    if kind == "shift":
+        back = G.shift(G.shift(it, [3.5], [2.7]), [-3.5], [-2.7])
+        ref = Q.double_shift(img[0], 3.5, 2.7)
+        spl = Q.spline_double_shift(img[0], 3.5, 2.7)
+    else:
+        back = G.rotate(G.rotate(it, [11.3]), [-11.3])
+        ref = Q.double_rotate(img[0], 11.3)
+        spl = Q.spline_double_rotate(img[0], 11.3)
+    got = back.cpu().numpy()[0]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 2 * REL_L2    # two passes of the shift / rotate bar
+    rms, counts = G.annular_rms(back, it, 2.0, 60)
+    want, rc = Q.annular_rms(got, img[0], 2.0, 60)
+    assert counts.cpu().numpy().tolist() == rc.tolist()
+    r = rms.cpu().numpy()[0]                                      # the one frame of the stack
+    assert np.all(np.abs(r - want) <= 1e-12 * want)
+    rs, _ = Q.annular_rms(spl, img[0], 2.0, 60)
+    assert np.all(r[1:50] * 3.0 < rs[1:50])                      # Fourier residuals far below spline ones

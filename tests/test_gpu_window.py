@@ -44,7 +44,7 @@ def _times_angles(T, seed):
     return t, a
 
 
-@pytest.mark.parametrize("T,N", [(1, 8), (5, 6), (64, 8), (65, 12), (130, 8), (2048, 8)])
+@pytest.mark.parametrize("T,N", [(1, 8), (5, 6), (64, 8), (65, 12), (130, 8), (300, 6), (600, 6), (2048, 8)])
 def test_median_window_bit_exact(torch_dev, T, N):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
