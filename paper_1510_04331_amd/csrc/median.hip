@@ -600,12 +600,14 @@ hipError_t launch_median_window(const float* stack, long long T, long long npix,
   (void)counts;   // the selection bits carry the counts
   if (T <= 0 || npix <= 0) return hipSuccess;
   const long long vpt = (T + kGroups - 1) / kGroups;
+  // pixels per block: at most about 50 KB of LDS, so that three blocks share
+  // a compute unit and their frame loops hide each other's latency
   if (vpt <= 1) return launch_window_v<1, 16>(stack, T, npix, sel, psf, resid, s);
   if (vpt <= 2) return launch_window_v<2, 16>(stack, T, npix, sel, psf, resid, s);
   if (vpt <= 4) return launch_window_v<4, 16>(stack, T, npix, sel, psf, resid, s);
   if (vpt <= 8) return launch_window_v<8, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 16) return launch_window_v<16, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 32) return launch_window_v<32, 8>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 16) return launch_window_v<16, 8>(stack, T, npix, sel, psf, resid, s);
+  if (vpt <= 32) return launch_window_v<32, 4>(stack, T, npix, sel, psf, resid, s);
   return hipErrorInvalidValue;   // T > 2048: rejected on the host before launch
 }
 
