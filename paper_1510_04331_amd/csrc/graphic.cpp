@@ -787,7 +787,7 @@ graphic_status do_median_window(graphic_ctx ctx, long long T, int N, const float
   auto* counts = reinterpret_cast<int*>(sel_ws + align_up((size_t)T * 64 * sizeof(unsigned long long)));
   Timer t(ctx, st, "median");
   hipError_t e = launch_select_frames(times, parang, T, t_max, alpha_min, sel, counts, st);
-  if (e == hipSuccess) e = launch_median_window(stack, T, (long long)N * N, sel, counts, psf, resid, st);
+  if (e == hipSuccess) e = launch_median_window(stack, T, (long long)N * N, sel, psf, resid, st);
   t.done();
   return hip_ok(e);
 }

@@ -128,7 +128,7 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
 // Per-frame medians over selected frames of a [T][npix] stack (T <= 2048):
 // psf[f] (nullable) and resid[f] = stack[f] - psf[f] (nullable, may be stack).
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
-                                const int* counts, float* psf, float* resid, hipStream_t s);
+                                float* psf, float* resid, hipStream_t s);
 
 // Registration (Sect. 2).  Per frame, out[f * kRegisterOut + k]: centroid x,
 // y, fitted x0, y0, I0, alpha, beta, Bg, final half sum of squared

@@ -218,7 +218,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
   static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
   constexpr bool TMS = (TM & 1) != 0, TMD = (TM & 2) != 0;
-  static_assert(!(TM & 3) || (M >= 1024 && (KIND == kColPass || G * JOB == 64)), "tile-major rows: one job per wave");
+  static_assert(!TM || (M >= 1024 && (KIND == kColPass || G * JOB == 64)), "tile-major rows: one job per wave");
   static_assert(!TMS || KIND == kRowPass, "tile-major sources are read by row passes");
   static_assert(!TMD || (KIND == kRowPass ? (IO == kIoWinWin || IO == kIoFullWin) : STG),
                 "tile-major destinations: window stores of row passes or staged column stores");

@@ -596,9 +596,7 @@ static hipError_t launch_window_v(const float* stack, long long T, long long npi
 }
 
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
-                                const int* counts, float* psf, float* resid, hipStream_t s) {
-  (void)counts;   // the selection bits carry the counts
-  if (T <= 0 || npix <= 0) return hipSuccess;
+                                float* psf, float* resid, hipStream_t s) {  if (T <= 0 || npix <= 0) return hipSuccess;
   const long long vpt = (T + kGroups - 1) / kGroups;
   // pixels per block: at most about 50 KB of LDS, so that three blocks share
   // a compute unit and their frame loops hide each other's latency
