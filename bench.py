@@ -547,8 +547,8 @@ def main():
     ap.add_argument("--traffic", default=os.path.join(HERE, "profiles", "traffic_adi_1024.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is described in "
-              "DESIGN.md, not implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (sharding over several GPUs is designed but not "
+              "implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
