@@ -380,7 +380,7 @@ void graphic_graph_destroy(graphic_graph graph);
  * geometry on the caller's device -- the tile width (jobs per block) of the
  * column passes for both line pairings, and the pixel tile (16 or 8) of the
  * median for this frame count, in the frame-major layout and, for the sizes
- * whose ADI workspace stack is tile-major (P = 2N, N >= 1024), in that
+ * whose ADI workspace stack is tile-major (P = 2N, N = 1024), in that
  * layout too -- and keeps the fastest in the context; later
  * calls with that geometry use them.  Every variant computes bit-identical
  * results.  It overwrites `ws` with synthetic frames and synchronises

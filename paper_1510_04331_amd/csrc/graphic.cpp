@@ -556,9 +556,10 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
     std::vector<ShiftItem> sh;
     std::vector<RotItem> rot;
     // Stacks that only the workspace holds are kept tile-major when the
-    // class has the canonical large geometry (P = 2N, N >= 1024): the
-    // medians then stream each 16-pixel run of the stack contiguously.
-    bool tm = ctx->tile_major && P == 2 * N && N >= 1024 && N <= kMaxM;
+    // class has the geometry where that pays (P = 2N, N = 1024): the medians
+    // then stream each 16-pixel run of the stack contiguously.  (At N = 2048
+    // the row passes, which already spill, lose as much as the medians gain.)
+    bool tm = ctx->tile_major && P == 2 * N && N == 1024;
     for (int i : c) {
       sh.push_back(ShiftItem{d[i].cube, stack[i], d[i].n_frames, d[i].dx, d[i].dy});
       rot.push_back(RotItem{stack[i], stack[i], d[i].n_frames, d[i].parang_deg});
@@ -1185,7 +1186,7 @@ graphic_status graphic_autotune(graphic_ctx ctx, const graphic_geom* geom, void*
     if (!ok) return GRAPHIC_ERR_HIP;
     ctx->med_var[median_class(T)] = pick;
     // the tile-major median of the large canonical sizes, the same way
-    if (P == 2 * N && N >= 1024) {
+    if (P == 2 * N && N == 1024) {
       for (int v = 0; v < 2 && ok; ++v) {
         const double ms = time_launches(st, 2, [&] {
           hipError_t e = launch_median_tile_major(buf, T, npix, out, buf, v, st);

@@ -65,7 +65,7 @@ struct LinePass {
   int frame_group;        // block order: 0 or 1 = frame by frame; g > 1 = the blocks of g
                           // consecutive frames interleaved, frame fastest
 
-  // Tile-major cube arrays (cube launches only, rows of N = P/2 >= 1024
+  // Tile-major cube arrays (cube launches only, rows of N = P/2 = 1024
   // pixels, window-to-window or window-to-full index patterns): the source
   // (src_tm) or destination (dst_tm) of every cube is a tile-major stack of
   // cubes[i].tm_T frames; *_fs, *_ls and *_ps are ignored for it.

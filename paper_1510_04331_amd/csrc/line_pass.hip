@@ -816,12 +816,12 @@ constexpr int col_jobs_alt() {
   return M == 256 ? 8 : M == 512 ? 16 : M == 1024 ? 4 : M == 2048 ? 4 : 0;
 }
 
-// Tile-major passes of the ADI reduction (M >= 1024, cube launches): the
+// Tile-major passes of the ADI reduction (M = 1024, cube launches): the
 // shift row pass (in place), the first and last rotation shears (source,
 // destination) and the shift column pass (destination).
 template <int M>
 static hipError_t launch_tile_major(const LinePass& p, int kind, int variant, hipStream_t st) {
-  if constexpr (M >= 1024) {
+  if constexpr (M == 1024) {
     const int tm = (p.src_tm ? 1 : 0) | (p.dst_tm ? 2 : 0);
     const int io = io_kind(p);
     if (p.n_cubes < 1 || (long long)M * 4 * p.cubes[0].tm_T > 0x7fffffffLL) return hipErrorInvalidValue;

@@ -1,5 +1,6 @@
-"""Tile-major workspace stacks of the ADI reduction (frames of N >= 1024
-pixels, P = 2N).
+"""Tile-major workspace stacks of the ADI reduction (frames of 1024 x 1024
+pixels, P = 2N; other sizes keep the frame-major stack, which the 2048 case
+checks through the same comparison).
 
 When the caller asks for no residuals and the cube is not overwritten, the
 reduction keeps its stack in the workspace in the tile-major layout (the
