@@ -49,7 +49,8 @@ def _small_ws(torch, dev, bytes_default, N, F, chunk):
     return torch.empty(bytes_default - (default_cf - chunk) * per_frame, dtype=torch.uint8, device=dev)
 
 
-@pytest.mark.parametrize("N,T,wide,chunk", [(1024, 37, True, None), (1024, 70, False, 6), (2048, 19, True, 4)])
+@pytest.mark.parametrize("N,T,wide,chunk", [(1024, 37, True, None), (1024, 70, False, 6), (1024, 1, True, None),
+                                             (1024, 64, True, 5), (2048, 19, True, 4)])
 def test_tile_major_equals_frame_major(torch_dev, N, T, wide, chunk):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
