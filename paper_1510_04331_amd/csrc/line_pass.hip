@@ -357,6 +357,12 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     ptab[tidx(n1)] = phase_exp((double)(2 * Mb) * (double)k1s, q, 1.0f / (float)P);
   }
 
+  // Waves issue their input loads at raised priority so that every wave's
+  // requests are in flight early; measured per pass: it helps the shift
+  // passes and the first shear, and slows the y-shear and the last shear.
+  constexpr bool kLoadPrio = !(KIND == kColPass && MIR) && IO != kIoFullWin;
+  if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(2);
+
   // ---- load, pack and fold into this half's branch ----
   const float sg = h ? -1.0f : 1.0f;
   const unsigned tw_lane = (unsigned)(h * M + n1) * 8u;
@@ -457,6 +463,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
     }
   }
+
+  if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(0);
 
   // ---- step A: length-Mb transforms over n2, twiddle ----
   Dft<Mb, -1>::run(v);
