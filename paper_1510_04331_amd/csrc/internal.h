@@ -94,6 +94,14 @@ struct LinePass {
 
 enum PassKind { kRowPass = 0, kColPass = 1 };
 
+// Raises a kernel's dynamic LDS limit to `bytes` before its launch; returns
+// the runtime's status so that a refused size stops the launch.
+template <typename Kernel>
+inline hipError_t set_dynamic_lds(Kernel* kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 // Index patterns of a pass (input support -> output window), see line_pass.hip.
 enum IoKind { kIoGeneric = 0, kIoWinWin = 1, kIoWinFull = 2, kIoFullWin = 3 };
 

@@ -763,17 +763,16 @@ static hipError_t launch_g(LinePass p, hipStream_t st) {
   const bool flipped = IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse);
   if ((TM & 2) && flipped) return hipErrorInvalidValue;   // the general path stores frame-major only
   const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_kernel<M, KIND, G, IO, MIR, TM>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = set_dynamic_lds(line_pass_kernel<M, KIND, G, IO, MIR, TM>, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR, TM>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st,
                      p);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess || !flipped) return e;
   // half-turned frames: general path over the device-side list
   constexpr int TMF = TM & 1;
   const size_t lds_flip = (size_t)lds_floats<M, KIND, G, false>() * sizeof(float);
-  hipFuncSetAttribute((const void*)line_pass_flipped_kernel<M, KIND, G, MIR, TMF>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_flip);
+  if ((e = set_dynamic_lds(line_pass_flipped_kernel<M, KIND, G, MIR, TMF>, lds_flip)) != hipSuccess) return e;
   const long long fb = std::min<long long>(blocks, 2048);
   hipLaunchKernelGGL((line_pass_flipped_kernel<M, KIND, G, MIR, TMF>), dim3((unsigned)fb), dim3(G * S::JOB), lds_flip,
                      st, p);

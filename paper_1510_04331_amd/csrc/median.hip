@@ -284,41 +284,49 @@ __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __r
 }
 
 // The same on a tile-major stack.  The block's kPix pixels (16, or 8 = one
-// half of a 16-pixel run) over all T frames lie in one run of 64 T bytes, and
-// thread (px, g) finds frame g + 64 i of its pixel at byte
-// ((g + 64 i) * 16 + px0 + px) * 4 of the run (px0: 0, or 8 for the second
-// half), so each load of a wave reads 64 / kPix frames of the tile from one
-// contiguous stretch.  Frame group i has its own wave-uniform descriptor
-// whose extent ends with frame T - 1, so frames past T read 0 and their
-// stores are dropped.  With kPix = 8, two blocks fit a compute unit.
+// half of a 16-pixel run) over all T frames lie in one run of 64 T bytes.
+// Thread (px, g) holds the VPT consecutive frames g VPT + i of its pixel, at
+// byte ((g VPT + i) * 16 + px0 + px) * 4 of the run (px0: 0, or 8 for the
+// second half): its loads and stores differ only by i * 64 bytes, which the
+// instructions' immediate offset carries, so one offset register and one
+// wave-uniform descriptor (extent 64 T bytes) serve all of them.  Frames past
+// T lie beyond the extent: they read 0 and their stores are dropped.  (The
+// select does not depend on which frames a thread holds.)  The register budget
+// is that of four waves per SIMD, so with kPix = 8 two blocks fit a compute
+// unit.
 template <int VPT, int kPix>
-__global__ void __launch_bounds__(kPix * kGroups) median_tm_kernel(const float* __restrict__ stack, long long T,
-                                                                   long long npix, float* __restrict__ out,
-                                                                   float* resid) {
+__global__ void __launch_bounds__(kPix * kGroups) __attribute__((amdgpu_waves_per_eu(4)))
+median_tm_kernel(const float* __restrict__ stack, long long T, long long npix, float* __restrict__ out, float* resid) {
   static_assert(kTilePix % kPix == 0, "a tile is a whole run or a part of one");
   extern __shared__ unsigned hist[];
   __shared__ SelShared<kPix> sh;
   const Tile<kPix> t(T, npix);
   const long long run0 = (t.pix0 / kTilePix) * T * kTilePix;         // float index of the run
-  const unsigned voff = (unsigned)(t.g * kTilePix + (int)(t.pix0 % kTilePix) + t.px) * 4u;
-  constexpr int kGroupFloats = kGroups * kTilePix;                   // 64 frames of the run
-  auto group_rsrc = [&](const float* base, int i) {
-    const long long left = (T - (long long)kGroups * i) * kTilePix * 4;
-    return frames_rsrc(base + run0 + (long long)i * kGroupFloats, left > 0 ? (unsigned)left : 0u);
-  };
+  const unsigned run_bytes = (unsigned)T * kTilePix * 4u;
+  const int f0 = t.g * VPT;                                          // this thread's first frame
+  const unsigned voff = (unsigned)(f0 * kTilePix + (int)(t.pix0 % kTilePix) + t.px) * 4u;
+  constexpr unsigned kFrameBytes = kTilePix * 4u;
+  static_assert((VPT - 1) * kFrameBytes < 4096u, "frame steps fit the 12-bit immediate offset");
+  const __amdgpu_buffer_rsrc_t src = frames_rsrc(stack + run0, run_bytes);
+  const int n_mine = t.Ti - f0;                                      // frames of this thread below T
   unsigned key[VPT];
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
-    const float v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(group_rsrc(stack, i), (int)voff, 0, 0));
-    key[i] = t.g + kGroups * i < t.Ti ? key_of(v) : 0xFFFFFFFFu;
+    const float v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(src, (int)(voff + i * kFrameBytes), 0, 0));
+    key[i] = i < n_mine ? key_of(v) : 0xFFFFFFFFu;
   }
   select_median<VPT, kPix>(t, key, ~0ull, (unsigned)T, hist, sh);
   const float med = sh.med[t.px];
   if (t.g == 0) out[t.pix] = med;
   if (resid != nullptr) {
+    const __amdgpu_buffer_rsrc_t dst = frames_rsrc(resid + run0, run_bytes);
+    // a fresh copy of the offset, so that the stores take i * 64 as their
+    // immediate offset instead of 64 offsets kept live across the select
+    unsigned soff = voff;
+    asm volatile("" : "+v"(soff));
 #pragma unroll
     for (int i = 0; i < VPT; ++i)
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), group_rsrc(resid, i), (int)voff,
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(val_of(key[i]) - med), dst, (int)(soff + i * kFrameBytes),
                                             0, 0);
   }
 }
@@ -552,13 +560,11 @@ static hipError_t launch_median_pix(const float* stack, long long T, long long n
 #define GRAPHIC_MEDIAN_CASE(V)                                                                              \
   if (vpt <= V) {                                                                                          \
     if (buf) {                                                                                             \
-      hipFuncSetAttribute((const void*)median_kernel<V, PIX, true>,                                        \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      if (hipError_t e = set_dynamic_lds(median_kernel<V, PIX, true>, lds); e != hipSuccess) return e;     \
       hipLaunchKernelGGL((median_kernel<V, PIX, true>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, T, \
                          npix, out, resid);                                                                \
     } else {                                                                                               \
-      hipFuncSetAttribute((const void*)median_kernel<V, PIX, false>,                                       \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      if (hipError_t e = set_dynamic_lds(median_kernel<V, PIX, false>, lds); e != hipSuccess) return e;    \
       hipLaunchKernelGGL((median_kernel<V, PIX, false>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, \
                          T, npix, out, resid);                                                             \
     }                                                                                                      \
@@ -589,7 +595,7 @@ static hipError_t launch_window_v(const float* stack, long long T, long long npi
   constexpr int TP = 64 * V;
   const size_t lds = (size_t)PB * TP * (sizeof(unsigned) + sizeof(unsigned short)) + (size_t)PB * (TP / 32) * 4;
   const unsigned blocks = (unsigned)((npix + PB - 1) / PB);
-  hipFuncSetAttribute((const void*)median_window_kernel<V, PB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipError_t e = set_dynamic_lds(median_window_kernel<V, PB>, lds); e != hipSuccess) return e;
   hipLaunchKernelGGL((median_window_kernel<V, PB>), dim3(blocks), dim3(PB * 64), lds, s, stack, T, npix, sel, psf,
                      resid);
   return hipGetLastError();
@@ -618,13 +624,11 @@ hipError_t launch_median_nan(const float* stack, long long T, long long npix, fl
 #define GRAPHIC_NAN_CASE(V)                                                                                 \
   if (vpt <= V) {                                                                                          \
     if (buf) {                                                                                             \
-      hipFuncSetAttribute((const void*)median_nan_kernel<V, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                          (int)lds);                                                                       \
+      if (hipError_t e = set_dynamic_lds(median_nan_kernel<V, true>, lds); e != hipSuccess) return e;      \
       hipLaunchKernelGGL((median_nan_kernel<V, true>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T, npix, \
                          out);                                                                             \
     } else {                                                                                               \
-      hipFuncSetAttribute((const void*)median_nan_kernel<V, false>,                                        \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                           \
+      if (hipError_t e = set_dynamic_lds(median_nan_kernel<V, false>, lds); e != hipSuccess) return e;     \
       hipLaunchKernelGGL((median_nan_kernel<V, false>), dim3(blocks), dim3(16 * kGroups), lds, s, stack, T,  \
                          npix, out);                                                                       \
     }                                                                                                      \
@@ -649,8 +653,7 @@ static hipError_t launch_median_tm_pix(const float* stack, long long T, long lon
   const size_t lds = (size_t)PIX * (64 / PIX) * kHistWords * sizeof(unsigned);
 #define GRAPHIC_TM_CASE(V)                                                                                  \
   if (vpt <= V) {                                                                                          \
-    hipFuncSetAttribute((const void*)median_tm_kernel<V, PIX>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
-                        (int)lds);                                                                         \
+    if (hipError_t e = set_dynamic_lds(median_tm_kernel<V, PIX>, lds); e != hipSuccess) return e;          \
     hipLaunchKernelGGL((median_tm_kernel<V, PIX>), dim3(blocks), dim3(PIX * kGroups), lds, s, stack, T, npix, \
                        out, resid);                                                                        \
     return hipGetLastError();                                                                              \

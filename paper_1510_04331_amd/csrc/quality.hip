@@ -96,7 +96,7 @@ hipError_t launch_annular_rms(const float* a, const float* b, long long T, int N
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = annular_rms_lds_bytes(n_rings);
-  hipFuncSetAttribute((const void*)ring_sum_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if ((e = set_dynamic_lds(ring_sum_kernel, lds)) != hipSuccess) return e;
   hipLaunchKernelGGL(ring_sum_kernel, dim3((unsigned)((N + kRows - 1) / kRows), (unsigned)T), dim3(kThreads), lds, s,
                      a, b, N, cx, cy, width, n_rings, rms, counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -292,7 +292,6 @@ register_kernel(const float* __restrict__ cube, long long T, int n, RegisterPara
   const int nfit = fw * fh;
   double lam = 1e-3, cost = 0.0;            // thread 0's solver state
   double Ap[21], g[kNJ];
-  int iters = 0;
   bool converged = false;
   for (int it = 0; it < prm.max_iter; ++it) {
     if (s_ctl[1]) {                         // accepted step (or start): normal equations at s_p
@@ -341,7 +340,6 @@ register_kernel(const float* __restrict__ cube, long long T, int n, RegisterPara
     }
     block_sum<1>(tc, s_red);
     if (tid == 0) {
-      ++iters;
       const bool better = tc[0] < cost && isfinite(tc[0]);
       double step = 0.0, size = 0.0;
       for (int a = 0; a < kNJ; ++a) {
