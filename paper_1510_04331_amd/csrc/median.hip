@@ -137,12 +137,18 @@ template <int VPT, int kPix, bool BUF>
 __device__ __forceinline__ void store_diff(const Tile<kPix>& t, float* resid, long long npix,
                                            const unsigned (&key)[VPT], const float (&med)[VPT]) {
   unsigned long long raddr = reinterpret_cast<unsigned long long>(resid + t.pix0);
+  // fresh copies of the group extents, so that the descriptors are rebuilt
+  // here instead of being kept live (64 of them) across the select
+  unsigned ext = t.extent, ext_last = t.extent_last;
+  int last = t.last;
+  asm volatile("" : "+s"(ext), "+s"(ext_last), "+s"(last));
 #pragma unroll
   for (int i = 0; i < VPT; ++i) {
     const float r = val_of(key[i]) - med[i];
     if constexpr (BUF) {
-      __builtin_amdgcn_raw_buffer_store_b32(
-          __float_as_int(r), frames_rsrc(reinterpret_cast<const float*>(raddr), t.group_ext(i)), (int)t.voff, 0, 0);
+      const unsigned e = i < last ? ext : (i == last ? ext_last : 0u);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(r), frames_rsrc(reinterpret_cast<const float*>(raddr), e),
+                                            (int)t.voff, 0, 0);
       raddr += t.gstride;
     } else {
       const int f = t.g + kGroups * i;
