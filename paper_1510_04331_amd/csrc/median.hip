@@ -176,16 +176,18 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
   }
   unsigned mask = 0u;
   bool single = false;                              // every pixel's bin holds one key
-#pragma unroll 1
+  // (unrolled, so that the first digit, whose prefix is empty, takes every
+  // taking-part key without the prefix test)
+#pragma unroll
   for (int d = 3; d >= 0; --d) {
     for (int i = t.tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
     __syncthreads();
     const unsigned prefix = sh.prefix[t.px];
     const int shft = 8 * d;
-    // (mask = 0 and prefix = 0 for the first digit: every taking-part key counts)
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
-      const bool in = ((bits >> i) & 1ull) != 0ull && (key[i] & mask) == prefix;
+      const bool part = ((bits >> i) & 1ull) != 0ull;
+      const bool in = d == 3 ? part : part && (key[i] & mask) == prefix;
       const unsigned bin = in ? ((key[i] >> shft) & 0xFFu) : (unsigned)kBins;
       atomicAdd(&my_hist[bin], 1u);
     }
