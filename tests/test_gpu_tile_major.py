@@ -7,9 +7,11 @@ reduction keeps its stack in the workspace in the tile-major layout (the
 values of 16 neighbouring pixels over all frames are one contiguous run);
 with residuals it works in the caller's frame-major array instead.  The
 arithmetic is identical, so both give the same bits.  The cases cover ragged
-frame counts, half-turned frames, rotation chunks that start inside a cube
-and batches of two cubes in one launch, and one reduction is checked against
-the oracle.
+frame counts (the tile-major median gives each thread ceil(T/64) consecutive
+frames, rounded up to a power of two: at T = 130 and T = 2500 the last
+threads hold a few frames or none), half-turned frames, rotation chunks that
+start inside a cube and batches of two cubes in one launch, and one reduction
+is checked against the oracle.
 """
 
 import multiprocessing as mp
@@ -50,7 +52,8 @@ def _small_ws(torch, dev, bytes_default, N, F, chunk):
 
 
 @pytest.mark.parametrize("N,T,wide,chunk", [(1024, 37, True, None), (1024, 70, False, 6), (1024, 1, True, None),
-                                             (1024, 64, True, 5), (2048, 19, True, 4)])
+                                             (1024, 64, True, 5), (1024, 130, True, None), (1024, 2500, False, None),
+                                             (2048, 19, True, 4)])
 def test_tile_major_equals_frame_major(torch_dev, N, T, wide, chunk):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
