@@ -174,20 +174,40 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
     sh.rank[t.tid] = Kt == 0u ? 0u : (Kt - 1u) / 2u;
     sh.lo[t.tid] = 0xFFFFFFFFu;
   }
+  // Without per-pixel key counts the sub-histograms are cleared with
+  // unrolled 16-byte stores (hist is 16-byte aligned and holds a whole number
+  // of vectors) and the digit loop is unrolled, so that the first digit,
+  // whose prefix is empty, takes every key without the prefix test.  With
+  // per-pixel counts (a 64-bit participation mask per thread, 1024 threads)
+  // either change makes the kernel spill, so that variant keeps the plain
+  // loops.
+  constexpr int kVec = kPix * kSub * kHistWords / 4;
+  static_assert((kPix * kSub * kHistWords) % 4 == 0, "whole 16-byte vectors");
+  auto zero_hist = [&]() {
+    if constexpr (PPK) {
+      for (int i = t.tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
+    } else {
+      uint4* h4 = reinterpret_cast<uint4*>(hist);
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int k = 0; k < kVec / kThreads; ++k) h4[t.tid + k * kThreads] = z;
+      if (kVec % kThreads != 0 && t.tid < kVec % kThreads) h4[(kVec / kThreads) * kThreads + t.tid] = z;
+    }
+  };
   unsigned mask = 0u;
   bool single = false;                              // every pixel's bin holds one key
-  // (unrolled, so that the first digit, whose prefix is empty, takes every
-  // taking-part key without the prefix test)
-#pragma unroll
+  constexpr int kDigitUnroll = PPK ? 1 : 4;
+#pragma unroll kDigitUnroll
   for (int d = 3; d >= 0; --d) {
-    for (int i = t.tid; i < kPix * kSub * kHistWords; i += kThreads) hist[i] = 0u;
+    zero_hist();
     __syncthreads();
     const unsigned prefix = sh.prefix[t.px];
     const int shft = 8 * d;
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const bool part = ((bits >> i) & 1ull) != 0ull;
-      const bool in = d == 3 ? part : part && (key[i] & mask) == prefix;
+      // (mask = 0 and prefix = 0 for the first digit)
+      const bool in = (!PPK && d == 3) ? part : part && (key[i] & mask) == prefix;
       const unsigned bin = in ? ((key[i] >> shft) & 0xFFu) : (unsigned)kBins;
       atomicAdd(&my_hist[bin], 1u);
     }
@@ -275,7 +295,7 @@ template <int VPT, int kPix, bool BUF>
 __global__ void __launch_bounds__(kPix * kGroups) median_kernel(const float* __restrict__ stack, long long T,
                                                                 long long npix, float* __restrict__ out,
                                                                 float* resid) {
-  extern __shared__ unsigned hist[];     // one sub-histogram per (pixel, lane group)
+  extern __shared__ __align__(16) unsigned hist[];     // one sub-histogram per (pixel, lane group)
   __shared__ SelShared<kPix> sh;
   const Tile<kPix> t(T, npix);
   unsigned key[VPT];
@@ -306,7 +326,7 @@ template <int VPT, int kPix>
 __global__ void __launch_bounds__(kPix * kGroups) __attribute__((amdgpu_waves_per_eu(4)))
 median_tm_kernel(const float* __restrict__ stack, long long T, long long npix, float* __restrict__ out, float* resid) {
   static_assert(kTilePix % kPix == 0, "a tile is a whole run or a part of one");
-  extern __shared__ unsigned hist[];
+  extern __shared__ __align__(16) unsigned hist[];
   __shared__ SelShared<kPix> sh;
   const Tile<kPix> t(T, npix);
   const long long run0 = (t.pix0 / kTilePix) * T * kTilePix;         // float index of the run
@@ -508,7 +528,7 @@ template <int VPT, bool BUF>
 __global__ void __launch_bounds__(16 * kGroups) median_nan_kernel(const float* __restrict__ stack, long long T,
                                                                   long long npix, float* __restrict__ out) {
   constexpr int kPix = 16;
-  extern __shared__ unsigned hist[];
+  extern __shared__ __align__(16) unsigned hist[];
   __shared__ SelShared<kPix> sh;
   __shared__ unsigned s_K[kPix];
   const Tile<kPix> t(T, npix);
