@@ -67,7 +67,12 @@ struct graphic_ctx_s {
   std::vector<Acc> acc;
   size_t chunk_bytes = kDefaultChunkBytes;
   bool tile_major = true;                 // workspace stacks of the large canonical sizes are tile-major
-  int frame_group = 64;                   // block order of the passes over tile-major stacks
+  // Block order of the row passes over tile-major stacks: blocks of this many
+  // consecutive frames are interleaved.  The x-shears, whose other side is a
+  // frame-major scratch, take smaller groups: with 64 they ran at one of two
+  // speeds from process to process, with 32 always at the faster one.
+  int frame_group = 64;                   // the shift's row pass
+  int frame_group_shear = 32;             // the two x-shears
   // tuned launch variants (-1: not tuned, the default variant 0 runs)
   int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass
   int med_var[8];                         // [log2 of the median's values per thread]
@@ -387,7 +392,7 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
     for (int k = 0; k < ncub; ++k)
       a.cubes[k] = CubeRef{it[c0 + k].src, nullptr, nullptr, start[c0 + k] - f0, it[c0 + k].T};
     a.src_tm = tm ? 1 : 0;
-    a.frame_group = tm ? ctx->frame_group : 0;
+    a.frame_group = tm ? ctx->frame_group_shear : 0;
     graphic_status s = run_pass(ctx, a, kRowPass, "shear_x1", st);
     if (s != GRAPHIC_OK) return s;
     // y-shear: every scratch column, window rows in and out (in place)
@@ -437,7 +442,7 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
     for (int k = 0; k < ncub; ++k)
       c.cubes[k] = CubeRef{nullptr, it[c0 + k].dst, nullptr, start[c0 + k] - f0, it[c0 + k].T};
     c.dst_tm = tm ? 1 : 0;
-    c.frame_group = tm ? ctx->frame_group : 0;
+    c.frame_group = tm ? ctx->frame_group_shear : 0;
     if ((s = run_pass(ctx, c, kRowPass, "shear_x2", st)) != GRAPHIC_OK) return s;
     f0 += nf;
   }
@@ -622,9 +627,9 @@ graphic_status graphic_create(graphic_ctx* out, int hip_device) {
     if (v > 0) c->chunk_bytes = (size_t)v << 20;
   }
   if (const char* env = std::getenv("GRAPHIC_TILE_MAJOR")) c->tile_major = std::atoi(env) != 0;
-  if (const char* env = std::getenv("GRAPHIC_FRAME_GROUP")) {
+  if (const char* env = std::getenv("GRAPHIC_FRAME_GROUP")) {   // every row pass
     const int v = std::atoi(env);
-    if (v >= 1 && v <= 4096) c->frame_group = v;
+    if (v >= 1 && v <= 4096) c->frame_group = c->frame_group_shear = v;
   }
   graphic_status s = build_tables(c);
   if (s != GRAPHIC_OK) {

@@ -52,7 +52,8 @@ def _small_ws(torch, dev, bytes_default, N, F, chunk):
 
 
 @pytest.mark.parametrize("N,T,wide,chunk", [(1024, 37, True, None), (1024, 70, False, 6), (1024, 1, True, None),
-                                             (1024, 64, True, 5), (1024, 130, True, None), (1024, 2500, False, None),
+                                             (1024, 64, True, 5), (1024, 32, True, None), (1024, 130, True, None),
+                                             (1024, 2500, False, None),
                                              (2048, 19, True, 4)])
 def test_tile_major_equals_frame_major(torch_dev, N, T, wide, chunk):
     torch, dev = torch_dev
