@@ -11,7 +11,9 @@
 // alternative) and all T values of each (kPix waves; lanes = kPix pixels x
 // 64/kPix frame groups, so every load reads 4 kPix contiguous bytes of a
 // frame).  Thread (pixel, g) keeps the keys of
-// frames g, g+64, g+128, ... in registers, so the stack is read from HBM once.
+// frames g, g+64, g+128, ... in registers (on a tile-major stack: the VPT
+// consecutive frames from g VPT on, VPT being ceil(T/64) rounded up to a
+// power of two), so the stack is read from HBM once.
 // The rank-(T-1)/2 key is found by a most-significant-digit-first radix select
 // with up to four 8-bit digits; each digit builds a 256-bin histogram per
 // pixel in LDS and one wave per pixel scans it.  Every lane of a wave owns a
