@@ -208,9 +208,19 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const bool part = ((bits >> i) & 1ull) != 0ull;
-      // (mask = 0 and prefix = 0 for the first digit)
-      const bool in = (!PPK && d == 3) ? part : part && (key[i] & mask) == prefix;
-      const unsigned bin = in ? ((key[i] >> shft) & 0xFFu) : (unsigned)kBins;
+      unsigned bin;
+      if constexpr (PPK) {
+        // (mask = 0 and prefix = 0 for the first digit)
+        const bool in = part && (key[i] & mask) == prefix;
+        bin = in ? ((key[i] >> shft) & 0xFFu) : (unsigned)kBins;
+      } else if (d == 3) {
+        bin = part ? key[i] >> 24 : (unsigned)kBins;               // empty prefix
+      } else {
+        // the prefix is zero in this digit and below, so (key ^ prefix) >>
+        // shft is the digit when the key carries the prefix and at least 256
+        // (the spare slot) when it does not
+        bin = part ? min((key[i] ^ prefix) >> shft, (unsigned)kBins) : (unsigned)kBins;
+      }
       atomicAdd(&my_hist[bin], 1u);
     }
     __syncthreads();
