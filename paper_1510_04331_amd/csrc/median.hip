@@ -274,9 +274,22 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
   unsigned lo_key;
   if (single) {
     const unsigned prefix = sh.prefix[t.px];
+    if constexpr (PPK) {
 #pragma unroll
-    for (int i = 0; i < VPT; ++i)
-      if (((bits >> i) & 1ull) != 0ull && (key[i] & mask) == prefix) atomicMin(&sh.lo[t.px], key[i]);
+      for (int i = 0; i < VPT; ++i)
+        if (((bits >> i) & 1ull) != 0ull && (key[i] & mask) == prefix) atomicMin(&sh.lo[t.px], key[i]);
+    } else {
+      // Every key takes part here.  The keys with the prefix are those whose
+      // key ^ prefix has no bit under the mask, and key ^ prefix keeps their
+      // order; every other key's key ^ prefix is larger.  So the thread's
+      // smallest key ^ prefix is its smallest key with the prefix when it has
+      // no bit under the mask, and then one atomic per thread suffices (the
+      // variant above keeps one per key: it has no register to spare).
+      unsigned vmin = 0xFFFFFFFFu;
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) vmin = min(vmin, key[i] ^ prefix);
+      atomicMin(&sh.lo[t.px], (vmin & mask) == 0u ? (vmin ^ prefix) : 0xFFFFFFFFu);
+    }
     __syncthreads();
     lo_key = sh.lo[t.px];
   } else {
