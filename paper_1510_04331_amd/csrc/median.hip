@@ -239,13 +239,14 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
         const unsigned incl = wave_incl_scan(x);
         const unsigned tot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
         const unsigned long long hit = __ballot(carry + incl > k);
-        if (found_bin < 0 && hit != 0ull) {
+        if (hit != 0ull) {                          // wave-uniform: the later blocks are not needed
           const int l0 = __ffsll((long long)hit) - 1;
           found_bin = blk * 64 + l0;
           const unsigned incl0 = (unsigned)__builtin_amdgcn_readlane((int)incl, l0);
           const unsigned x0 = (unsigned)__builtin_amdgcn_readlane((int)x, l0);
           below = carry + incl0 - x0;
           inbin = x0;
+          break;
         }
         carry += tot;
       }
@@ -300,9 +301,20 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
   // hits lo iff it falls inside that run, otherwise hi is the smallest
   // taking-part key above lo.
   unsigned local_min = 0xFFFFFFFFu;
+  if constexpr (PPK) {
 #pragma unroll
-  for (int i = 0; i < VPT; ++i)
-    if (((bits >> i) & 1ull) != 0ull && key[i] > lo_key && key[i] < local_min) local_min = key[i];
+    for (int i = 0; i < VPT; ++i)
+      if (((bits >> i) & 1ull) != 0ull && key[i] > lo_key && key[i] < local_min) local_min = key[i];
+  } else if (lo_key != 0xFFFFFFFFu) {
+    // key - (lo + 1) wraps for the keys at or below lo, above every value
+    // of a key above lo, so the smallest of them gives the smallest key
+    // above lo (every key takes part here); the largest key stays "none"
+    const unsigned base = lo_key + 1u;
+    unsigned dmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) dmin = min(dmin, key[i] - base);
+    local_min = dmin <= 0xFFFFFFFEu - lo_key ? dmin + base : 0xFFFFFFFFu;
+  }
   atomicMin(&sh.min[t.px], local_min);
   __syncthreads();
   if (t.g == 0) {
