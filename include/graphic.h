@@ -47,7 +47,7 @@
  *   - A failed launch returns GRAPHIC_ERR_HIP.  Device-side faults surface at
  *     the caller's next synchronisation.
  *   - Non-finite input values are a precondition violation; the output is then
- *     unspecified.
+ *     unspecified.  The GRAPHIC_CHECK_FINITE geometry flag validates them.
  */
 #ifndef GRAPHIC_H
 #define GRAPHIC_H
@@ -70,7 +70,8 @@ typedef enum {
     GRAPHIC_ERR_UNSUPPORTED = 2,  /* valid but unsupported geometry */
     GRAPHIC_ERR_WORKSPACE = 3,    /* workspace null, too small or misaligned */
     GRAPHIC_ERR_HIP = 4,          /* a HIP runtime call failed */
-    GRAPHIC_ERR_NOMEM = 5         /* the context could not allocate its tables */
+    GRAPHIC_ERR_NOMEM = 5,        /* the context could not allocate its tables */
+    GRAPHIC_ERR_NONFINITE = 6     /* GRAPHIC_CHECK_FINITE found a NaN or inf input */
 } graphic_status;
 
 /* Operation codes for graphic_workspace_size. */
@@ -90,8 +91,29 @@ typedef struct {
     int64_t n_frames;   /* T >= 1 */
     int32_t n;          /* N: even, 4 <= N <= 4096 */
     int32_t pad;        /* P: power of two, N <= P <= 4096, 16 <= P; 0 => default */
-    uint32_t flags;     /* reserved, must be 0 */
+    uint32_t flags;     /* GRAPHIC_KEEP_PADDED | GRAPHIC_CHECK_FINITE, as each entry point allows; else 0 */
 } graphic_geom;
+
+/* Flags of graphic_geom.
+ *
+ * GRAPHIC_KEEP_PADDED (graphic_shift, graphic_rotate): the output is the
+ *   whole zero-padded working frame, out[T][P][P], instead of its N x N
+ *   window; the input stays [T][N][N] and must not overlap the output unless
+ *   P == N and out == in.  The operations of Sect. 3.3.1 and 3.4 are defined
+ *   on the padded frame: with this flag an integer shift is an exact circular
+ *   roll of it, a quarter turn an exact permutation, and the sum over the
+ *   padded frame (the DC term of every line) is kept.  The flux sums of the
+ *   output then run over the P x P frame.
+ *
+ * GRAPHIC_CHECK_FINITE (graphic_shift, graphic_rotate, graphic_median,
+ *   graphic_adi_reduce, graphic_median_window, graphic_adi_reduce_window):
+ *   before any other launch the call scans every float input (frames and
+ *   per-frame parameters) for NaN and +-inf on `stream`, waits for the scan
+ *   (the call synchronises `stream`, so it cannot be captured into a graph)
+ *   and returns GRAPHIC_ERR_NONFINITE, with nothing else launched, if it
+ *   found one.  The scan reads each input once more. */
+#define GRAPHIC_KEEP_PADDED 1u
+#define GRAPHIC_CHECK_FINITE 2u
 
 /* Create a context on HIP device `hip_device` (builds the twiddle tables on
  * that device).  Returns GRAPHIC_ERR_HIP if the device is unusable. */
@@ -118,7 +140,8 @@ graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geo
 
 /*
  * Fourier shift of every frame (Sect. 3.3.1, 2-D shift equation).
- *   in, out : [T][N][N] float32 device arrays; out == in is allowed.
+ *   in, out : [T][N][N] float32 device arrays; out == in is allowed.  With
+ *             GRAPHIC_KEEP_PADDED, out is [T][P][P] (see the flag).
  *   dx, dy  : [T] float64 device arrays, content displacement in pixels.
  *   flux    : NULL, or a [T][2] float64 device array receiving, per frame, the
  *             sum of the input frame and the sum of the output frame.
@@ -134,8 +157,11 @@ graphic_status graphic_shift(graphic_ctx ctx, const graphic_geom* geom,
 
 /*
  * Three-shear Fourier rotation of every frame (Sect. 3.4).
- *   in, out   : [T][N][N] float32 device arrays; out == in is allowed.
- *   theta_deg : [T] float64 device array, counter-clockwise angle in degrees.
+ *   in, out   : [T][N][N] float32 device arrays; out == in is allowed.  With
+ *               GRAPHIC_KEEP_PADDED, out is [T][P][P] (see the flag).
+ *   theta_deg : [T] float64 device array, counter-clockwise angle in degrees;
+ *               any finite angle (the rotation has period 360 degrees, and
+ *               the angle is first reduced to [-180, 180]).
  *   flux      : NULL or [T][2] float64 (input sum, output sum) per frame.
  *   ws        : graphic_workspace_size(GRAPHIC_OP_ROTATE) bytes.
  */
@@ -182,6 +208,7 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
  * paper prints the minimum rotation as 2 sin(n FWHM / (2 r_min)); callers
  * derive alpha_min_deg as the chord angle 2 arcsin(n FWHM / (2 r_min)).)
  * Frame i never selects itself unless alpha_min_deg < 0 or the fallback applies.
+ * graphic_alpha_min_deg gives alpha_min_deg from the paper's parameters.
  *   stack     : [T][N][N] float32, T <= 2048.
  *   times     : [T] float64 observing times (any unit, the unit of t_max).
  *   parang_deg: [T] float64 parallactic angles.
@@ -200,6 +227,16 @@ graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, 
                                      void* ws, size_t ws_bytes, graphic_stream stream);
 
 /*
+ * Minimum field rotation of the frame selection (Sect. 3.3): the angle, in
+ * degrees, through which a point at radius r_min (px) turns to move n_fwhm
+ * times fwhm (px) along its chord, 2 arcsin(n_fwhm fwhm / (2 r_min)).  (The
+ * paper prints 2 sin(...); the chord angle is the reading taken.)  Host-only,
+ * needs no context.  Errors: GRAPHIC_ERR_ARG for a null out_deg, non-finite
+ * arguments, r_min <= 0, or n_fwhm fwhm outside [0, 2 r_min].
+ */
+graphic_status graphic_alpha_min_deg(double n_fwhm, double fwhm, double r_min, double* out_deg);
+
+/*
  * ADI reduction with the per-frame PSF of graphic_median_window:
  * S_i = shift(cube_i), R_i = S_i - PSF_i, D_i = rotate(R_i, -parang_i),
  * final = median_i D_i.  Arguments as graphic_adi_reduce, plus the selection
@@ -213,7 +250,7 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
                                          void* ws, size_t ws_bytes, graphic_stream stream);
 
 /*
- * Registration (Sect. 2).
+ * Registration (Sect. 3.1).
  *
  * graphic_parallactic_angles: per-frame parallactic angle in degrees from the
  * local sidereal time (seconds), with hour angle h = 15 LST / 3600 - ra_deg:
@@ -221,7 +258,7 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
  * (the two-argument arctangent fixes the quadrant).  lst_s, out: [T] float64.
  *
  * graphic_register: per frame (one block each), the star centroid and a
- * Moffat fit (Sect. 2.2).  The centroid is the centre of mass, weighted by
+ * Moffat fit (Sect. 3.1.2).  The centroid is the centre of mass, weighted by
  * pixel values, of the 4-connected patch of pixels above `threshold` that
  * holds the brightest pixel, grown inside a 64 x 64 box around it; a patch
  * whose size lies outside [min_size, max_size] fails and the brightest pixel
@@ -234,8 +271,9 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
  * unmasked pixel.  Pixel (x, y) is column x, row y; the recentring shift of
  * graphic_shift is (N/2 - x0, N/2 - y0).  FWHM = 2 alpha sqrt(2^(1/beta) - 1).
  *   cube  : [T][N][N] float32.
- *   out   : [T][9] float64: centroid x, y; x0, y0, I0, alpha, beta, Bg; the
- *           final half sum of squared residuals.
+ *   out   : [T][12] float64: centroid x, y; x0, y0, I0, alpha, beta, Bg; the
+ *           final half sum of squared residuals; the FWHM of the fitted
+ *           profile; the recentring shift dx = N/2 - x0, dy = N/2 - y0.
  *   flags : [T] int32: bit 0 centroid patch found, bit 1 fit converged.
  * Errors: GRAPHIC_ERR_ARG for null pointers, half outside 1..32, min_size >
  * max_size or max_iter < 1; geometry errors as graphic_shift.
@@ -255,10 +293,10 @@ graphic_status graphic_register(graphic_ctx ctx, const graphic_geom* geom, const
                                 graphic_stream stream);
 
 /*
- * Image pre-processing (Sect. 3.1-3.2).  Frames as graphic_geom (T <= 65535).
+ * Image pre-processing (Sect. 3.2).  Frames as graphic_geom (T <= 65535).
  *
  * graphic_median_nan: per-pixel median of a stack ignoring NaN values, as
- *   graphic_median over the values left (the master sky of Sect. 3.1 after
+ *   graphic_median over the values left (the master sky of Sect. 3.2.1 after
  *   the star is masked); a pixel with no value left is NaN.  T <= 4096.
  * graphic_mask_disk: sets to NaN, in place, the pixels of frame i with
  *   (x - xs[i])^2 + (y - ys[i])^2 <= radius^2 (x column, y row; xs, ys [T]
@@ -294,7 +332,7 @@ graphic_status graphic_badpix_fix(graphic_ctx ctx, const graphic_geom* geom, flo
                                   graphic_stream stream);
 
 /*
- * Image-quality test (Sect. 4): the paper shifts an image by (3.5, 2.7) px
+ * Image-quality test (Sect. 4.1): the paper shifts an image by (3.5, 2.7) px
  * and back, or rotates it by 11.3 deg and back, subtracts the original and
  * plots the root mean square of the difference in concentric annuli.  The
  * round trips are graphic_shift / graphic_rotate calls; this entry point

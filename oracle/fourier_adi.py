@@ -30,14 +30,15 @@ Conventions (the paper leaves these open; the readings are fixed here once):
   lines and an integer shift is an exact circular roll.
 """
 
+import math
+
 import numpy as np
 
 __all__ = [
     "padded_size", "pad", "crop", "signed_freq", "phasor", "shift",
-    "shift_line", "shear_rows", "shear_cols", "flip180", "rotate",
-    "median_f32", "median_f64", "adi_reduce", "flux", "dft_matrix",
-    "dirichlet_kernel", "alpha_min_deg", "select_frames", "median_window_f32",
-    "adi_reduce_window",
+    "shear_rows", "shear_cols", "flip180", "reduce_angle", "rotate",
+    "median_f32", "median_f64", "adi_reduce", "dirichlet_kernel",
+    "alpha_min_deg", "select_frames", "median_window_f32", "adi_reduce_window",
 ]
 
 
@@ -102,13 +103,6 @@ def phasor(P, s):
     return phi
 
 
-def dft_matrix(P):
-    """Explicit DFT matrix exp(-2 pi i k n / P) (the paper's transform)."""
-    k = np.arange(P)[:, None]
-    n = np.arange(P)[None, :]
-    return np.exp(-2j * np.pi * k * n / P)
-
-
 def dirichlet_kernel(u, P):
     """Periodic band-limited interpolation kernel of the shift.
 
@@ -130,6 +124,10 @@ def dirichlet_kernel(u, P):
 # ---------------------------------------------------------------------------
 
 def _real_part(z, what):
+    # With the symmetric Nyquist phasor the product spectrum is Hermitian, so
+    # the exact inverse is real; what is left is float64 rounding of the
+    # transforms (about 1e-15 of the peak).  The guard sits at 1e-9 of the
+    # peak so that it only trips on a broken phasor, never on rounding.
     re = z.real
     scale = max(np.max(np.abs(re)), 1e-300)
     if np.max(np.abs(z.imag)) > 1e-9 * scale:
@@ -152,14 +150,6 @@ def shift(f, dx, dy, P=None, keep_padded=False):
     G = G * phasor(P, dy)[:, None] * phasor(P, dx)[None, :]
     out = _real_part(np.fft.ifft2(G), "shift")
     return out if keep_padded else crop(out, n)
-
-
-def shift_line(line, s):
-    """One-dimensional Fourier shift of a periodic real line by ``s``."""
-    line = np.asarray(line, dtype=np.float64)
-    P = line.shape[0]
-    z = np.fft.ifft(np.fft.fft(line) * phasor(P, s))
-    return _real_part(z, "shift_line")
 
 
 # ---------------------------------------------------------------------------
@@ -189,15 +179,26 @@ def flip180(g):
     return g[idx][:, idx]
 
 
+def reduce_angle(theta_deg):
+    """The angle in [-180, 180] degrees with the same rotation matrix.
+
+    R_theta (Sect. 3.4) is periodic in theta with period 360 degrees, while
+    tan(theta/2) of the shear factors is not bounded on a period: the angle is
+    first brought to the period around zero (IEEE remainder, exact in float64).
+    """
+    return math.remainder(float(theta_deg), 360.0)
+
+
 def rotate(f, theta_deg, P=None, keep_padded=False, padded_input=False):
     """Turn the content of ``f`` counter-clockwise by ``theta_deg`` about c.
 
-    Content at ``c + u`` ends at ``c + R_theta u``.  The three shears act in
-    the order x, y, x: rows move by ``-tan(theta/2) (y - c)``, then columns by
-    ``sin(theta) (x - c)``, then rows again by ``-tan(theta/2) (y - c)``
-    (Sect. 3.4, shear equations).  For |theta| > 90 degrees an exact half-turn
-    is applied first and theta is reduced by 180 degrees, so tan(theta/2)
-    stays bounded.
+    Content at ``c + u`` ends at ``c + R_theta u``.  The angle is first
+    reduced to [-180, 180] degrees (:func:`reduce_angle`).  The three shears
+    act in the order x, y, x: rows move by ``-tan(theta/2) (y - c)``, then
+    columns by ``sin(theta) (x - c)``, then rows again by
+    ``-tan(theta/2) (y - c)`` (Sect. 3.4, shear equations).  For |theta| > 90
+    degrees an exact half-turn is applied first and theta is reduced by 180
+    degrees, so tan(theta/2) stays bounded.
     """
     f = np.asarray(f, dtype=np.float64)
     if padded_input:
@@ -208,7 +209,7 @@ def rotate(f, theta_deg, P=None, keep_padded=False, padded_input=False):
         n = f.shape[0]
         P = padded_size(n) if P is None else int(P)
         g = pad(f, P)
-    th = float(theta_deg)
+    th = reduce_angle(theta_deg)
     if abs(th) > 90.0:
         g = flip180(g)
         th = th - 180.0 * np.sign(th)
@@ -355,9 +356,3 @@ def adi_reduce_window(cube, dx, dy, parang_deg, times, t_max, alpha_min, P=None,
     final = median_f64(derot)
     return {"final": final, "psf": psf, "shifted": shifted, "derotated": derot, "sel": sel}
 
-
-def flux(frame):
-    """Total flux (plain float64 sum) of a frame; the Fourier operations keep
-    the DC term of every line, so the sum over the padded frame is invariant
-    (abstract: flux conservation)."""
-    return float(np.sum(np.asarray(frame, dtype=np.float64)))

@@ -1,4 +1,4 @@
-"""FP64 / float32 CPU oracle of the image pre-processing (Sect. 3.1 and 3.2
+"""FP64 / float32 CPU oracle of the image pre-processing (Sect. 3.2, 3.2.1 and 3.2.2
 of Hagelberg et al. 2016, arXiv:1510.04331): master sky and bad pixels.
 
 TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``.  It shares no code
@@ -67,7 +67,7 @@ def subtract_nearest(cube, times, skies, sky_times):
 
 
 def badpix_map(frame, c_sigma):
-    """Boolean map of the bad pixels of one frame (Sect. 3.2)."""
+    """Boolean map of the bad pixels of one frame (Sect. 3.2.2)."""
     f = np.asarray(frame, dtype=np.float32)
     fin = np.isfinite(f)
     vals = f[fin]

@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of the image-quality test of Sect. 4 of Hagelberg et al.
+"""FP64 CPU oracle of the image-quality test of Sect. 4.1 of Hagelberg et al.
 2016 (arXiv:1510.04331): an image is shifted (or rotated) and moved back,
 the original is subtracted, and the root mean square of the difference is
 taken in concentric annuli around the frame centre.

@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of the registration step (Sect. 2 of Hagelberg et al. 2016,
+"""FP64 CPU oracle of the registration step (Sect. 3.1 of Hagelberg et al. 2016,
 arXiv:1510.04331): parallactic angles, star centroid and Moffat fit.
 
 TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: only the test-suite,
@@ -7,7 +7,7 @@ shares no code with the HIP library.
 
 Readings (the paper leaves these open; the HIP path follows the same ones):
 
-* Parallactic angle: the arctangent of Sect. 2.1 is taken with its two
+* Parallactic angle: the arctangent of Sect. 3.1.1 is taken with its two
   arguments (atan2), which fixes the quadrant; the hour angle is
   h = 15 LST / 3600 - RA in degrees (LST in seconds, RA in degrees).
 * Centroid: the patch is the 4-connected set of pixels above the threshold
@@ -15,7 +15,7 @@ Readings (the paper leaves these open; the HIP path follows the same ones):
   that pixel; its centre of mass uses the pixel values as weights.  A patch
   whose size falls outside [min_size, max_size] fails, and the brightest
   pixel stands in for the centroid.
-* Moffat fit: the model of Sect. 2.2 over a (2 half) x (2 half) box around the
+* Moffat fit: the model of Sect. 3.1.2 over a (2 half) x (2 half) box around the
   rounded centroid, pixels at or above the saturation level (and non-finite
   ones) masked out, least squares with MINPACK's Levenberg-Marquardt (lmdif,
   the routine the paper names) from the starting point below.
@@ -34,7 +34,7 @@ BOX = 64          # side of the centroid search box
 
 
 def parallactic_angle(lst_s, ra_deg, dec_deg, lat_deg):
-    """Parallactic angle in degrees (Sect. 2.1): hour angle from the local
+    """Parallactic angle in degrees (Sect. 3.1.1): hour angle from the local
     sidereal time (seconds) and right ascension (degrees), then
     atan2(cos(phi) sin(h), cos(delta) sin(phi) - sin(delta) cos(phi) cos(h))."""
     h = np.radians(15.0 * np.asarray(lst_s, dtype=np.float64) / 3600.0 - ra_deg)
@@ -50,7 +50,7 @@ def _box(n, c, side):
 
 def centroid(frame, threshold, min_size, max_size):
     """Centre of mass of the contiguous patch above ``threshold`` holding the
-    brightest pixel (Sect. 2.2, first stage).  Returns (x, y, ok, size)."""
+    brightest pixel (Sect. 3.1.2, first stage).  Returns (x, y, ok, size)."""
     from scipy import ndimage
     f = np.asarray(frame, dtype=np.float64)
     n = f.shape[0]
@@ -74,14 +74,14 @@ def centroid(frame, threshold, min_size, max_size):
 
 def moffat(p, x, y):
     """I0 (beta - 1) / (pi alpha^2) (1 + ((x - x0)^2 + (y - y0)^2) / alpha^2)^-beta + Bg
-    with p = (I0, x0, y0, alpha, beta, Bg) (Sect. 2.2)."""
+    with p = (I0, x0, y0, alpha, beta, Bg) (Sect. 3.1.2)."""
     i0, xc, yc, a, b, bg = p
     u = 1.0 + ((x - xc) ** 2 + (y - yc) ** 2) / a ** 2
     return i0 * (b - 1.0) / (np.pi * a ** 2) * u ** (-b) + bg
 
 
 def moffat_fwhm(alpha, beta):
-    """FWHM = 2 alpha sqrt(2^(1/beta) - 1) (Sect. 2.2)."""
+    """FWHM = 2 alpha sqrt(2^(1/beta) - 1) (Sect. 3.1.2)."""
     return 2.0 * alpha * np.sqrt(2.0 ** (1.0 / beta) - 1.0)
 
 

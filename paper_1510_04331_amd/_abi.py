@@ -11,7 +11,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgraphic.so")
 
 # status codes (graphic_status)
-OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM = range(6)
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM, ERR_NONFINITE = range(7)
+# graphic_geom.flags
+KEEP_PADDED, CHECK_FINITE = 1, 2
 (OP_SHIFT, OP_ROTATE, OP_ADI, OP_MEDIAN, OP_MEDIAN_WINDOW, OP_ADI_WINDOW, OP_BADPIX_MAP,
  OP_BADPIX_FIX) = range(8)
 
@@ -19,7 +21,8 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOMEM = range(6)
 EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
     "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
-    "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_adi_reduce_window",
+    "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_alpha_min_deg",
+    "graphic_adi_reduce_window",
     "graphic_parallactic_angles", "graphic_register", "graphic_median_nan", "graphic_mask_disk",
     "graphic_subtract_nearest", "graphic_badpix_map", "graphic_badpix_fix", "graphic_annular_rms",
     "graphic_batch_workspace_size", "graphic_adi_reduce_batch",
@@ -91,6 +94,8 @@ def load():
     f64 = ctypes.c_double
     lib.graphic_median_window.argtypes = [vp, g, vp, vp, vp, f64, f64, vp, vp, vp, sz, vp]
     lib.graphic_median_window.restype = st
+    lib.graphic_alpha_min_deg.argtypes = [f64, f64, f64, ctypes.POINTER(f64)]
+    lib.graphic_alpha_min_deg.restype = st
     lib.graphic_adi_reduce_window.argtypes = [vp, g, vp, vp, vp, vp, vp, f64, f64, vp, vp, vp, vp, sz, vp]
     lib.graphic_adi_reduce_window.restype = st
     lib.graphic_parallactic_angles.argtypes = [vp, vp, i64, f64, f64, f64, vp, vp]

@@ -9,15 +9,17 @@ namespace graphic {
 namespace {
 
 // Three-shear factors of Sect. 3.4 for every frame: the rotation R(theta) is
-// S_x(-tan(theta/2)) S_y(sin theta) S_x(-tan(theta/2)).  For |theta| > 90
-// degrees an exact half-turn is taken out first (flip = 1) and theta is
-// reduced by 180 degrees toward zero, so that tan(theta/2) stays bounded.
+// S_x(-tan(theta/2)) S_y(sin theta) S_x(-tan(theta/2)).  R(theta) has period
+// 360 degrees, so theta is first brought to [-180, 180] (IEEE remainder,
+// exact).  For |theta| > 90 degrees an exact half-turn is then taken out
+// (flip = 1) and theta is reduced by 180 degrees toward zero, so that
+// tan(theta/2) stays bounded.
 __global__ void rotation_params_kernel(const double* __restrict__ theta_deg, double sign, long long T,
                                        int* __restrict__ flip, double* __restrict__ neg_tan_half,
                                        double* __restrict__ sin_theta) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T) return;
-  double th = sign * theta_deg[i];
+  double th = remainder(sign * theta_deg[i], 360.0);
   int fl = 0;
   if (fabs(th) > 90.0) {
     fl = 1;
@@ -74,7 +76,51 @@ __global__ void __launch_bounds__(256) fill_noise_kernel(float* __restrict__ p, 
   }
 }
 
+// Non-finite scan: *flag becomes 1 if any of the n values is NaN or +-inf
+// (exponent bits all set).  Reads float4 / double2 where the base allows;
+// the flag is only written by a block that found one.
+__global__ void __launch_bounds__(256) clear_flag_kernel(int* __restrict__ flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+__global__ void __launch_bounds__(256) nonfinite_f32_kernel(const float* __restrict__ p, size_t n,
+                                                            int* __restrict__ flag) {
+  int bad = 0;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    bad |= (__float_as_uint(p[i]) & 0x7f800000u) == 0x7f800000u;
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(256) nonfinite_f64_kernel(const double* __restrict__ p, size_t n,
+                                                            int* __restrict__ flag) {
+  int bad = 0;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    bad |= ((unsigned long long)__double_as_longlong(p[i]) & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
 }  // namespace
+
+hipError_t launch_clear_flag(int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(256), 0, s, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_f32(const float* p, size_t n, int* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(nonfinite_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_f64(const double* p, size_t n, int* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(nonfinite_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, flag);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s) {
   if (n == 0) return hipSuccess;

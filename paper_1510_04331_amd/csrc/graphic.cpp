@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,7 +56,8 @@ struct TimingSlot {
 
 struct graphic_ctx_s {
   int device = 0;
-  void* tables = nullptr;                 // one device allocation for every M
+  void* tables = nullptr;                 // one device allocation for every M (and the scan flag)
+  int* scan_flag = nullptr;               // device int of the non-finite scan, after the tables
   TwiddleTables tw[16] = {};              // indexed by log2(M)
   bool timing = false;
   std::vector<TimingSlot> pending;
@@ -125,8 +127,9 @@ graphic_status build_tables(graphic_ctx ctx) {
     std::memcpy(&host[off + 2 * M], fo.data(), 2 * M * sizeof(float2));
     off += 4 * M;
   }
-  if (hipMalloc(&ctx->tables, total) != hipSuccess) return GRAPHIC_ERR_NOMEM;
+  if (hipMalloc(&ctx->tables, total + 256) != hipSuccess) return GRAPHIC_ERR_NOMEM;
   if (hipMemcpy(ctx->tables, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return GRAPHIC_ERR_HIP;
+  ctx->scan_flag = reinterpret_cast<int*>(static_cast<char*>(ctx->tables) + total);
   int idx = 0;
   for (int M = kMinM; M <= kMaxM; M *= 2, ++idx) {
     const float2* base = static_cast<const float2*>(ctx->tables) + offs[idx];
@@ -143,9 +146,12 @@ graphic_status build_tables(graphic_ctx ctx) {
 // ---------------------------------------------------------------------------
 bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 
-graphic_status check_geom(const graphic_geom* g, int* P_out) {
+constexpr uint32_t kAllFlags = GRAPHIC_KEEP_PADDED | GRAPHIC_CHECK_FINITE;
+
+// Geometry checks; `allowed` is the set of geom flags the caller accepts.
+graphic_status check_geom(const graphic_geom* g, int* P_out, uint32_t allowed = 0) {
   if (!g) return GRAPHIC_ERR_ARG;
-  if (g->flags != 0) return GRAPHIC_ERR_ARG;
+  if ((g->flags & ~allowed) != 0) return GRAPHIC_ERR_ARG;
   if (g->n_frames < 1) return GRAPHIC_ERR_ARG;
   if (g->n < 4 || g->n > 4096 || (g->n % 2) != 0) return GRAPHIC_ERR_ARG;
   int P = g->pad;
@@ -167,6 +173,20 @@ bool overlap_bad(const void* a, const void* b, size_t bytes) {
   const char* x = static_cast<const char*>(a);
   const char* y = static_cast<const char*>(b);
   return x < y + bytes && y < x + bytes;
+}
+
+// [a, a + abytes) and [b, b + bbytes) share a byte.
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bbytes && y < x + abytes;
+}
+
+// Input [T][N][N] and output [T][P][P] of a GRAPHIC_KEEP_PADDED call: no
+// shared byte, except out == in when P == N.
+bool padded_overlap_bad(const void* in, const void* out, long long T, int N, int P) {
+  if (P == N) return overlap_bad(in, out, (size_t)T * N * N * sizeof(float));
+  return ranges_overlap(in, (size_t)T * N * N * sizeof(float), out, (size_t)T * P * P * sizeof(float));
 }
 
 // ---------------------------------------------------------------------------
@@ -449,6 +469,187 @@ graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it,
   return GRAPHIC_OK;
 }
 
+// Whole zero-padded output (GRAPHIC_KEEP_PADDED) of the shift: the column
+// pass takes the N window columns to all P rows of the P x P output, then the
+// row pass takes every output row's N window columns to all P columns, in
+// place (the columns outside the window are never read).  Each job loads its
+// two lines before it stores them, and jobs own disjoint lines.
+graphic_status do_shift_padded(graphic_ctx ctx, int N, int P, long long T, const float* in, float* out,
+                               const double* dx, const double* dy, hipStream_t st) {
+  const int o = (P - N) / 2;
+  LinePass c = base_pass(ctx, P);
+  c.src = in;
+  c.dst = out;
+  c.src_fs = (long long)N * N;
+  c.dst_fs = (long long)P * P;
+  c.src_ls = c.dst_ls = 1;
+  c.src_ps = N;
+  c.dst_ps = P;
+  c.line_lo = o;
+  c.n_lines = N;
+  c.in_off = o;
+  c.in_len = N;
+  c.out_off = 0;
+  c.out_len = P;
+  c.dst_line_lo = 0;
+  c.n_jobs = N / 2;
+  c.n_frames = T;
+  c.sh0 = dy;
+  graphic_status s = run_pass(ctx, c, kColPass, "shift_y", st);
+  if (s != GRAPHIC_OK) return s;
+  // A pass reads its support [in_off, in_off + in_len) from positions
+  // 0 .. in_len - 1 of the source line: the row pass's source lines start at
+  // the window's first column.
+  LinePass r = base_pass(ctx, P);
+  r.src = out + o;
+  r.dst = out;
+  r.src_fs = r.dst_fs = (long long)P * P;
+  r.src_ls = r.dst_ls = P;
+  r.src_ps = r.dst_ps = 1;
+  r.line_lo = 0;
+  r.n_lines = P;
+  r.in_off = o;
+  r.in_len = N;
+  r.out_off = 0;
+  r.out_len = P;
+  r.dst_line_lo = 0;
+  r.n_jobs = P / 2;
+  r.n_frames = T;
+  r.sh0 = dx;
+  return run_pass(ctx, r, kRowPass, "shift_x", st);
+}
+
+// Whole zero-padded output (GRAPHIC_KEEP_PADDED) of the rotation: the first
+// x-shear as in do_rotate_batch (window rows to all P columns of the
+// scratch), the y-shear from the scratch's window rows to all P rows of the
+// P x P output, and the second x-shear over every output row, whole line to
+// whole line, in place.
+graphic_status do_rotate_padded(graphic_ctx ctx, int N, int P, long long T, const float* in, float* out,
+                                const double* theta, void* ws, size_t ws_bytes, hipStream_t st) {
+  RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, ws_bytes);
+  if (L.chunk_frames < 1) return GRAPHIC_ERR_WORKSPACE;
+  char* w = static_cast<char*>(ws);
+  int* flip = reinterpret_cast<int*>(w);
+  double* ntan = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)));
+  double* sn = reinterpret_cast<double*>(w + align_up((size_t)T * sizeof(int)) + align_up((size_t)T * sizeof(double)));
+  int* flip_list = reinterpret_cast<int*>(w + align_up((size_t)T * sizeof(int)) + 2 * align_up((size_t)T * sizeof(double)));
+  int* flip_count = reinterpret_cast<int*>(reinterpret_cast<char*>(flip_list) + align_up((size_t)T * sizeof(int)));
+  float* scratch = reinterpret_cast<float*>(w + L.params);
+  {
+    Timer t(ctx, st, "aux");
+    hipError_t e = launch_rotation_params(theta, 1.0, T, flip, ntan, sn, st);
+    t.done();
+    if (e != hipSuccess) return GRAPHIC_ERR_HIP;
+  }
+  const int o = (P - N) / 2;
+  for (long long f0 = 0; f0 < T;) {
+    const long long nf = std::min<long long>((long long)L.chunk_frames, T - f0);
+    {
+      Timer t(ctx, st, "aux");
+      hipError_t e = launch_flip_list(flip, f0, nf, flip_list, flip_count, st);
+      t.done();
+      if (e != hipSuccess) return GRAPHIC_ERR_HIP;
+    }
+    LinePass a = base_pass(ctx, P);
+    a.src = in + (size_t)f0 * N * N;
+    a.dst = scratch;
+    a.src_fs = (long long)N * N;
+    a.dst_fs = (long long)N * P;
+    a.src_ls = N;
+    a.src_ps = 1;
+    a.dst_ls = P;
+    a.dst_ps = 1;
+    a.line_lo = o;
+    a.n_lines = N;
+    a.in_off = o;
+    a.in_len = N;
+    a.out_off = 0;
+    a.out_len = P;
+    a.dst_line_lo = o;
+    a.mirror = 1;
+    a.n_jobs = N / 2 + 1;
+    a.n_frames = nf;
+    a.sh1 = ntan + f0;
+    a.flip = flip + f0;
+    a.flip_list = flip_list;
+    a.flip_count = flip_count;
+    a.flip_src_reverse = 1;
+    a.flip_lines = 1;
+    a.flip_in_off = 1;
+    graphic_status s = run_pass(ctx, a, kRowPass, "shear_x1", st);
+    if (s != GRAPHIC_OK) return s;
+    float* dst = out + (size_t)f0 * P * P;
+    LinePass b = base_pass(ctx, P);
+    b.src = scratch;
+    b.dst = dst;
+    b.src_fs = (long long)N * P;
+    b.dst_fs = (long long)P * P;
+    b.src_ls = b.dst_ls = 1;
+    b.src_ps = b.dst_ps = P;
+    b.line_lo = 0;
+    b.n_lines = P;
+    b.in_off = o;
+    b.in_len = N;
+    b.out_off = 0;
+    b.out_len = P;
+    b.dst_line_lo = 0;
+    b.mirror = 1;
+    b.n_jobs = P / 2 + 1;
+    b.n_frames = nf;
+    b.sh1 = sn + f0;
+    b.flip = flip + f0;
+    b.flip_list = flip_list;
+    b.flip_count = flip_count;
+    b.flip_in_off = 1;
+    if ((s = run_pass(ctx, b, kColPass, "shear_y", st)) != GRAPHIC_OK) return s;
+    LinePass c = base_pass(ctx, P);
+    c.src = dst;
+    c.dst = dst;
+    c.src_fs = c.dst_fs = (long long)P * P;
+    c.src_ls = c.dst_ls = P;
+    c.src_ps = c.dst_ps = 1;
+    c.line_lo = 0;
+    c.n_lines = P;
+    c.in_off = 0;
+    c.in_len = P;
+    c.out_off = 0;
+    c.out_len = P;
+    c.dst_line_lo = 0;
+    c.mirror = 1;
+    c.n_jobs = P / 2 + 1;
+    c.n_frames = nf;
+    c.sh1 = ntan + f0;
+    if ((s = run_pass(ctx, c, kRowPass, "shear_x2", st)) != GRAPHIC_OK) return s;
+    f0 += nf;
+  }
+  return GRAPHIC_OK;
+}
+
+// GRAPHIC_CHECK_FINITE: scan the float32 and float64 inputs on the stream,
+// wait, and report whether any value is NaN or +-inf.
+struct ScanF32 {
+  const float* p;
+  size_t n;
+};
+struct ScanF64 {
+  const double* p;
+  size_t n;
+};
+
+graphic_status check_finite(graphic_ctx ctx, hipStream_t st, std::initializer_list<ScanF32> f32,
+                            std::initializer_list<ScanF64> f64) {
+  if (launch_clear_flag(ctx->scan_flag, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+  for (const ScanF32& a : f32)
+    if (a.p && launch_nonfinite_f32(a.p, a.n, ctx->scan_flag, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+  for (const ScanF64& a : f64)
+    if (a.p && launch_nonfinite_f64(a.p, a.n, ctx->scan_flag, st) != hipSuccess) return GRAPHIC_ERR_HIP;
+  int h = 0;
+  if (hipMemcpyAsync(&h, ctx->scan_flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GRAPHIC_ERR_HIP;
+  return h ? GRAPHIC_ERR_NONFINITE : GRAPHIC_OK;
+}
+
 graphic_status do_median(graphic_ctx ctx, long long T, int N, const float* stack, float* out, float* resid,
                          hipStream_t st, bool tm = false) {
   Timer t(ctx, st, "median");
@@ -526,8 +727,10 @@ graphic_status plan_batch(const graphic_cube_desc* d, int n, uint32_t flags, siz
   return GRAPHIC_OK;
 }
 
+// With check_fin, every cube and parameter array is scanned for non-finite
+// values after the argument checks and before the reduction's launches.
 graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uint32_t flags, void* ws,
-                         size_t ws_bytes, hipStream_t st) {
+                         size_t ws_bytes, hipStream_t st, bool check_fin = false) {
   BatchPlan plan;
   graphic_status s = plan_batch(d, n, flags, ctx->chunk_bytes, &plan);
   if (s != GRAPHIC_OK) return s;
@@ -546,6 +749,12 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
   }
   if (!ws_ok(ws, ws_bytes, plan.fixed + plan.rot_min)) return GRAPHIC_ERR_WORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  for (int i = 0; i < n && check_fin; ++i) {
+    const size_t T = (size_t)d[i].n_frames;
+    s = check_finite(ctx, st, {{d[i].cube, T * d[i].n * d[i].n}},
+                     {{d[i].dx, T}, {d[i].dy, T}, {d[i].parang_deg, T}});
+    if (s != GRAPHIC_OK) return s;
+  }
   char* w = static_cast<char*>(ws);
   std::vector<float*> stack(n), psf(n);
   for (int i = 0; i < n; ++i) {
@@ -603,6 +812,7 @@ const char* graphic_status_string(graphic_status s) {
     case GRAPHIC_ERR_WORKSPACE: return "GRAPHIC_ERR_WORKSPACE: workspace missing, too small or misaligned";
     case GRAPHIC_ERR_HIP: return "GRAPHIC_ERR_HIP: HIP runtime error";
     case GRAPHIC_ERR_NOMEM: return "GRAPHIC_ERR_NOMEM: out of device memory";
+    case GRAPHIC_ERR_NONFINITE: return "GRAPHIC_ERR_NONFINITE: an input holds NaN or inf";
   }
   return "GRAPHIC: unknown status";
 }
@@ -611,7 +821,7 @@ const char* graphic_version(void) { return "graphic-mi355x 0.1 (gfx950)"; }
 
 int32_t graphic_resolved_pad(const graphic_geom* geom) {
   int P = 0;
-  return check_geom(geom, &P) == GRAPHIC_OK ? P : -1;
+  return check_geom(geom, &P, kAllFlags) == GRAPHIC_OK ? P : -1;
 }
 
 graphic_status graphic_create(graphic_ctx* out, int hip_device) {
@@ -653,7 +863,7 @@ void graphic_destroy(graphic_ctx ctx) {
 graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geom* geom, size_t* bytes) {
   if (!bytes) return GRAPHIC_ERR_ARG;
   int P = 0;
-  graphic_status s = check_geom(geom, &P);
+  graphic_status s = check_geom(geom, &P, kAllFlags);
   if (s != GRAPHIC_OK) return s;
   const size_t chunk = ctx ? ctx->chunk_bytes : kDefaultChunkBytes;
   const long long T = geom->n_frames;
@@ -694,20 +904,29 @@ graphic_status graphic_shift(graphic_ctx ctx, const graphic_geom* geom, const fl
                              graphic_stream stream) {
   int P = 0;
   if (!ctx) return GRAPHIC_ERR_ARG;
-  graphic_status s = check_geom(geom, &P);
+  graphic_status s = check_geom(geom, &P, kAllFlags);
   if (s != GRAPHIC_OK) return s;
   if (!in || !out || !dx || !dy) return GRAPHIC_ERR_ARG;
   const long long T = geom->n_frames;
   const int N = geom->n;
+  const bool padded = (geom->flags & GRAPHIC_KEEP_PADDED) != 0;
+  const int No = padded ? P : N;             // output frame side
   const size_t bytes = (size_t)T * N * N * sizeof(float);
-  if (overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
+  if (padded ? padded_overlap_bad(in, out, T, N, P) : overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
   if (!ws_ok(ws, ws_bytes, shift_ws(T, N, P))) return GRAPHIC_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  if ((geom->flags & GRAPHIC_CHECK_FINITE) &&
+      (s = check_finite(ctx, st, {{in, (size_t)T * N * N}}, {{dx, (size_t)T}, {dy, (size_t)T}})) != GRAPHIC_OK)
+    return s;
   if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
-  const ShiftItem item{in, out, T, dx, dy};
-  if ((s = do_shift_batch(ctx, N, P, &item, 1, st)) != GRAPHIC_OK) return s;
-  if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
+  if (padded) {
+    if ((s = do_shift_padded(ctx, N, P, T, in, out, dx, dy, st)) != GRAPHIC_OK) return s;
+  } else {
+    const ShiftItem item{in, out, T, dx, dy};
+    if ((s = do_shift_batch(ctx, N, P, &item, 1, st)) != GRAPHIC_OK) return s;
+  }
+  if (flux && (s = do_sums(ctx, T, No, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
 }
 
@@ -716,22 +935,33 @@ graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom, const f
                               graphic_stream stream) {
   int P = 0;
   if (!ctx) return GRAPHIC_ERR_ARG;
-  graphic_status s = check_geom(geom, &P);
+  graphic_status s = check_geom(geom, &P, kAllFlags);
   if (s != GRAPHIC_OK) return s;
   if (!in || !out || !theta_deg) return GRAPHIC_ERR_ARG;
   const long long T = geom->n_frames;
   const int N = geom->n;
+  const bool padded = (geom->flags & GRAPHIC_KEEP_PADDED) != 0;
+  const int No = padded ? P : N;
   const size_t bytes = (size_t)T * N * N * sizeof(float);
-  if (overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
+  // the padded path reads every input frame of a chunk before its last pass
+  // writes the output, so it needs disjoint arrays (or P == N, out == in)
+  if (padded ? padded_overlap_bad(in, out, T, N, P) : overlap_bad(in, out, bytes)) return GRAPHIC_ERR_ARG;
   RotLayout need = rot_layout(T, N, P, ctx->chunk_bytes, 0);
   const size_t minimum = need.params + align_up((size_t)N * P * sizeof(float));
   if (!ws_ok(ws, ws_bytes, minimum)) return GRAPHIC_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  if ((geom->flags & GRAPHIC_CHECK_FINITE) &&
+      (s = check_finite(ctx, st, {{in, (size_t)T * N * N}}, {{theta_deg, (size_t)T}})) != GRAPHIC_OK)
+    return s;
   if (flux && (s = do_sums(ctx, T, N, in, flux, 0, st)) != GRAPHIC_OK) return s;
-  const RotItem item{in, out, T, theta_deg};
-  if ((s = do_rotate_batch(ctx, N, P, &item, 1, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
-  if (flux && (s = do_sums(ctx, T, N, out, flux, 1, st)) != GRAPHIC_OK) return s;
+  if (padded) {
+    if ((s = do_rotate_padded(ctx, N, P, T, in, out, theta_deg, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
+  } else {
+    const RotItem item{in, out, T, theta_deg};
+    if ((s = do_rotate_batch(ctx, N, P, &item, 1, 1.0, ws, ws_bytes, st)) != GRAPHIC_OK) return s;
+  }
+  if (flux && (s = do_sums(ctx, T, No, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
 }
 
@@ -740,7 +970,7 @@ graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const f
   (void)ws;
   (void)ws_bytes;
   if (!ctx || !geom || !stack || !out) return GRAPHIC_ERR_ARG;
-  if (geom->n_frames < 1 || geom->n < 1 || geom->flags != 0) return GRAPHIC_ERR_ARG;
+  if (geom->n_frames < 1 || geom->n < 1 || (geom->flags & ~GRAPHIC_CHECK_FINITE) != 0) return GRAPHIC_ERR_ARG;
   if (geom->n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
   const long long T = geom->n_frames;
   const int N = geom->n;
@@ -748,14 +978,19 @@ graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const f
       (out >= stack && out < stack + (size_t)T * N * N))
     return GRAPHIC_ERR_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
-  return do_median(ctx, T, N, stack, out, nullptr, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (geom->flags & GRAPHIC_CHECK_FINITE) {
+    graphic_status s = check_finite(ctx, st, {{stack, (size_t)T * N * N}}, {});
+    if (s != GRAPHIC_OK) return s;
+  }
+  return do_median(ctx, T, N, stack, out, nullptr, st);
 }
 
 graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, const float* cube, const double* dx,
                                   const double* dy, const double* parang_deg, float* final_img, float* psf,
                                   float* residuals, void* ws, size_t ws_bytes, graphic_stream stream) {
   if (!ctx || !geom) return GRAPHIC_ERR_ARG;
-  if (geom->flags != 0) return GRAPHIC_ERR_ARG;
+  if ((geom->flags & ~GRAPHIC_CHECK_FINITE) != 0) return GRAPHIC_ERR_ARG;
   graphic_cube_desc d;
   d.cube = cube;
   d.n_frames = geom->n_frames;
@@ -767,7 +1002,8 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom, con
   d.final_img = final_img;
   d.psf = psf;
   d.residuals = residuals;
-  return adi_batch(ctx, &d, 1, 0u, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return adi_batch(ctx, &d, 1, 0u, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                   (geom->flags & GRAPHIC_CHECK_FINITE) != 0);
 }
 
 }  // extern "C"
@@ -777,7 +1013,7 @@ namespace {
 graphic_status window_args(graphic_ctx ctx, const graphic_geom* geom, const void* times, const void* parang,
                            double t_max, double alpha_min, int* P) {
   if (!ctx || !geom || !times || !parang) return GRAPHIC_ERR_ARG;
-  graphic_status s = check_geom(geom, P);
+  graphic_status s = check_geom(geom, P, GRAPHIC_CHECK_FINITE);
   if (s != GRAPHIC_OK) return s;
   if (geom->n_frames > kMaxT_Window) return GRAPHIC_ERR_UNSUPPORTED;
   if (std::isnan(t_max) || std::isnan(alpha_min)) return GRAPHIC_ERR_ARG;
@@ -818,8 +1054,21 @@ graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, 
   if (psf_cube && resid && (overlap_bad(psf_cube, resid, cube_b) || psf_cube == resid)) return GRAPHIC_ERR_ARG;
   if (!ws_ok(ws, ws_bytes, window_sel_bytes(T))) return GRAPHIC_ERR_WORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  if ((geom->flags & GRAPHIC_CHECK_FINITE) &&
+      (s = check_finite(ctx, static_cast<hipStream_t>(stream), {{stack, (size_t)T * N * N}},
+                        {{times, (size_t)T}, {parang_deg, (size_t)T}})) != GRAPHIC_OK)
+    return s;
   return do_median_window(ctx, T, N, stack, times, parang_deg, t_max, alpha_min_deg, psf_cube, resid,
                           static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+graphic_status graphic_alpha_min_deg(double n_fwhm, double fwhm, double r_min, double* out_deg) {
+  if (!out_deg || !std::isfinite(n_fwhm) || !std::isfinite(fwhm) || !std::isfinite(r_min) || !(r_min > 0.0))
+    return GRAPHIC_ERR_ARG;
+  const double x = n_fwhm * fwhm / (2.0 * r_min);
+  if (!(x >= 0.0 && x <= 1.0)) return GRAPHIC_ERR_ARG;
+  *out_deg = 2.0 * std::asin(x) * (180.0 / 3.14159265358979323846);
+  return GRAPHIC_OK;
 }
 
 graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* geom, const float* cube,
@@ -850,6 +1099,11 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
   if (!ws_ok(ws, ws_bytes, fixed + L.params + align_up((size_t)N * P * sizeof(float)))) return GRAPHIC_ERR_WORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((geom->flags & GRAPHIC_CHECK_FINITE) &&
+      (s = check_finite(ctx, st, {{cube, (size_t)T * N * N}},
+                        {{dx, (size_t)T}, {dy, (size_t)T}, {parang_deg, (size_t)T}, {times, (size_t)T}})) !=
+          GRAPHIC_OK)
+    return s;
   char* w = static_cast<char*>(ws);
   float* stack = residuals ? residuals : reinterpret_cast<float*>(w);
   ShiftItem sh{cube, stack, T, dx, dy};

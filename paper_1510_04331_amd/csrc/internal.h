@@ -138,9 +138,10 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
                                 float* psf, float* resid, hipStream_t s);
 
-// Registration (Sect. 2).  Per frame, out[f * kRegisterOut + k]: centroid x,
+// Registration (Sect. 3.1).  Per frame, out[f * kRegisterOut + k]: centroid x,
 // y, fitted x0, y0, I0, alpha, beta, Bg, final half sum of squared
-// residuals; flags[f]: bit 0 centroid patch found, bit 1 fit converged.
+// residuals, Moffat FWHM, recentring shift dx = N/2 - x0, dy = N/2 - y0;
+// flags[f]: bit 0 centroid patch found, bit 1 fit converged.
 struct RegisterParams {
   double threshold;      // patch threshold
   int min_size, max_size;  // accepted patch sizes (pixels)
@@ -148,7 +149,7 @@ struct RegisterParams {
   double saturation;     // pixels at or above it are masked in the fit
   int max_iter;          // Levenberg-Marquardt iterations
 };
-constexpr int kRegisterOut = 9;
+constexpr int kRegisterOut = 12;
 hipError_t launch_register(const float* cube, long long T, int n, const RegisterParams& prm, double* out,
                            int* flags, hipStream_t s);
 hipError_t launch_parallactic(const double* lst_s, long long T, double ra_deg, double dec_deg, double lat_deg,
@@ -157,7 +158,7 @@ hipError_t launch_parallactic(const double* lst_s, long long T, double ra_deg, d
 // NaN-ignoring per-pixel median (NaN where no value is left), T <= 4096.
 hipError_t launch_median_nan(const float* stack, long long T, long long npix, float* out, hipStream_t s);
 
-// Pre-processing (Sect. 3.1-3.2); frames are indexed by the grid's y, T <= 65535.
+// Pre-processing (Sect. 3.2); frames are indexed by the grid's y, T <= 65535.
 hipError_t launch_mask_disk(float* cube, long long T, int n, const double* xs, const double* ys, double radius,
                             hipStream_t s);
 hipError_t launch_subtract_nearest(float* cube, long long T, int n, const double* times, const float* skies,
@@ -168,7 +169,7 @@ hipError_t launch_badpix_map(const float* frame, int n, double c_sigma, unsigned
 hipError_t launch_apply_map(float* cube, long long T, int n, const unsigned char* map, hipStream_t s);
 hipError_t launch_repair_pass(const float* src, float* dst, long long T, int n, int* flags, hipStream_t s);
 
-// Image-quality test (Sect. 4): RMS of a - b (b nullable) in n_rings annuli
+// Image-quality test (Sect. 4.1): RMS of a - b (b nullable) in n_rings annuli
 // of width `width` around (cx, cy), per frame of [T][N][N] stacks, into
 // rms[T][n_rings] (NaN: empty annulus) and counts[n_rings] (pixels per
 // annulus); n_rings <= kMaxRings, T <= 65535.
@@ -178,6 +179,12 @@ hipError_t launch_annular_rms(const float* a, const float* b, long long T, int N
 
 // n floats of seeded noise around a sky level (for timing runs on scratch).
 hipError_t launch_fill_noise(float* p, size_t n, unsigned seed, hipStream_t s);
+
+// Non-finite scan: launch_clear_flag sets *flag = 0; the scans set it to 1
+// if any of the n values is NaN or +-inf.
+hipError_t launch_clear_flag(int* flag, hipStream_t s);
+hipError_t launch_nonfinite_f32(const float* p, size_t n, int* flag, hipStream_t s);
+hipError_t launch_nonfinite_f64(const double* p, size_t n, int* flag, hipStream_t s);
 
 // Per-frame float64 sums of [T][N][N] frames into flux[2*t + slot].
 hipError_t launch_frame_sums(const float* frames, long long T, int N, double* flux, int slot,

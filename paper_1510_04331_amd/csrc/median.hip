@@ -559,7 +559,7 @@ median_window_kernel(const float* __restrict__ stack, long long T, long long npi
   }
 }
 
-// Per-pixel median ignoring NaN values (the master sky of Sect. 3.1: star
+// Per-pixel median ignoring NaN values (the master sky of Sect. 3.2.1: star
 // regions are NaN); a pixel with no value left is NaN.
 template <int VPT, bool BUF>
 __global__ void __launch_bounds__(16 * kGroups) median_nan_kernel(const float* __restrict__ stack, long long T,

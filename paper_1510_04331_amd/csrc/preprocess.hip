@@ -1,4 +1,4 @@
-// Image pre-processing (Sect. 3.1 and 3.2): star masks, nearest-sky
+// Image pre-processing (Sect. 3.2, 3.2.1 and 3.2.2): star masks, nearest-sky
 // subtraction, the bad pixel map of one frame (median and standard deviation
 // of its finite pixels) and the neighbour repair of bad pixels.
 //

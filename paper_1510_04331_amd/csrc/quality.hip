@@ -1,4 +1,4 @@
-// Image-quality test of Sect. 4 (gfx950): the root mean square of a - b in
+// Image-quality test of Sect. 4.1 (gfx950): the root mean square of a - b in
 // concentric annuli around (cx, cy), per frame.  The paper applies it to the
 // difference between an image and its double-shifted (there and back) or
 // double-rotated copy; the shifts and rotations are the library's own passes.

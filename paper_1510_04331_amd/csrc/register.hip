@@ -1,4 +1,4 @@
-// Registration (Sect. 2): parallactic angles, star centroid and Moffat fit.
+// Registration (Sect. 3.1): parallactic angles, star centroid and Moffat fit.
 //
 // One block of 256 threads registers one frame:
 //   1. the brightest pixel (non-finite values never win; ties go to the first
@@ -7,7 +7,7 @@
 //      grown inside a 64 x 64 box in LDS, and the patch's centre of mass
 //      weighted by pixel values (a patch size outside [min, max] fails and
 //      the brightest pixel stands in);
-//   3. a least-squares fit of the Moffat profile of Sect. 2.2,
+//   3. a least-squares fit of the Moffat profile of Sect. 3.1.2,
 //        I0 (beta - 1) / (pi alpha^2) (1 + r^2 / alpha^2)^-beta + Bg,
 //      over a (2 half)^2 box around the rounded centroid, saturated and
 //      non-finite pixels masked, by Levenberg-Marquardt in float64 with
@@ -373,6 +373,12 @@ register_kernel(const float* __restrict__ cube, long long T, int n, RegisterPara
     o[6] = s_p[4];
     o[7] = s_p[5];
     o[8] = cost;
+    // FWHM of the fitted Moffat profile (Sect. 3.1.2): the radius where the
+    // profile falls to half its peak, doubled
+    o[9] = 2.0 * s_p[3] * sqrt(exp2(1.0 / s_p[4]) - 1.0);
+    // recentring shift that brings the fitted centre to pixel (N/2, N/2)
+    o[10] = 0.5 * (double)n - s_p[1];
+    o[11] = 0.5 * (double)n - s_p[2];
     flags[f] = (s_cok ? 1 : 0) | (converged ? 2 : 0);
   }
 }

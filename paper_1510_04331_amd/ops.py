@@ -23,8 +23,8 @@ def context(device_index):
     return ctx
 
 
-def _geom(T, N, pad):
-    return _abi.Geom(int(T), int(N), int(pad or 0), 0)
+def _geom(T, N, pad, flags=0):
+    return _abi.Geom(int(T), int(N), int(pad or 0), int(flags))
 
 
 def _stream(dev):
@@ -58,6 +58,34 @@ def _check_cube(x, name="cube"):
     return x.shape[0], x.shape[1]
 
 
+def _check_out(out, shape, device, name="out"):
+    """A caller-supplied output must be a contiguous float32 tensor of exactly
+    the result's shape on the input's device (the kernels write that many
+    values through its pointer)."""
+    import torch
+    if not isinstance(out, torch.Tensor):
+        raise ValueError("%s must be a tensor" % name)
+    if out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("%s must be a contiguous float32 tensor" % name)
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, not %s" % (name, tuple(shape), tuple(out.shape)))
+    if out.device != device:
+        raise ValueError("%s must be on %s, not %s" % (name, device, out.device))
+    return out
+
+
+def _flags(keep_padded=False, check_finite=False):
+    return (_abi.KEEP_PADDED if keep_padded else 0) | (_abi.CHECK_FINITE if check_finite else 0)
+
+
+def resolved_pad(N, pad=None):
+    """Working size P of an N x N frame (pad, or the default next_pow2(2N))."""
+    P = _abi.load().graphic_resolved_pad(ctypes.byref(_geom(1, N, pad)))
+    if P < 0:
+        raise ValueError("unsupported frame size N=%d pad=%s" % (N, pad))
+    return P
+
+
 def _f64(v, T, dev, name):
     import torch
     t = torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous()
@@ -81,55 +109,64 @@ def _workspace(op, T, N, pad, dev):
     return torch.empty(max(n, 256), dtype=torch.uint8, device=dev), n
 
 
-def shift(cube, dx, dy, pad=None, out=None, flux=False):
+def shift(cube, dx, dy, pad=None, out=None, flux=False, keep_padded=False, check_finite=False):
     """Fourier shift of every frame by (dx[i], dy[i]) pixels (content moves
-    toward +x, +y).  Returns ``out`` (and a [T, 2] float64 flux tensor)."""
+    toward +x, +y).  Returns ``out`` (and a [T, 2] float64 flux tensor).
+    With ``keep_padded`` the result is the whole zero-padded [T, P, P] frame;
+    with ``check_finite`` non-finite inputs raise GraphicError."""
     import torch
     T, N = _check_cube(cube)
     dev = cube.device
     dx, dy = _f64(dx, T, dev, "dx"), _f64(dy, T, dev, "dy")
-    out = torch.empty_like(cube) if out is None else out
-    _check_cube(out, "out")
+    No = resolved_pad(N, pad) if keep_padded else N
+    if out is None:
+        out = torch.empty((T, No, No), dtype=torch.float32, device=dev)
+    _check_out(out, (T, No, No), dev)
     fl = torch.empty((T, 2), dtype=torch.float64, device=dev) if flux else None
     ws, n = _workspace(_abi.OP_SHIFT, T, N, pad, dev)
-    g = _geom(T, N, pad)
+    g = _geom(T, N, pad, _flags(keep_padded, check_finite))
     lib = _abi.load()
     _abi.check(lib.graphic_shift(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(out), _ptr(dx),
                                  _ptr(dy), _ptr(fl), _ptr(ws), n, _stream(dev)), "graphic_shift")
     return (out, fl) if flux else out
 
 
-def rotate(cube, theta_deg, pad=None, out=None, flux=False):
+def rotate(cube, theta_deg, pad=None, out=None, flux=False, keep_padded=False, check_finite=False):
     """Three-shear Fourier rotation of every frame by theta_deg[i] degrees
-    (counter-clockwise, centre at pixel (N/2, N/2))."""
+    (counter-clockwise, centre at pixel (N/2, N/2)).  ``keep_padded`` and
+    ``check_finite`` as for :func:`shift`."""
     import torch
     T, N = _check_cube(cube)
     dev = cube.device
     th = _f64(theta_deg, T, dev, "theta_deg")
-    out = torch.empty_like(cube) if out is None else out
-    _check_cube(out, "out")
+    No = resolved_pad(N, pad) if keep_padded else N
+    if out is None:
+        out = torch.empty((T, No, No), dtype=torch.float32, device=dev)
+    _check_out(out, (T, No, No), dev)
     fl = torch.empty((T, 2), dtype=torch.float64, device=dev) if flux else None
     ws, n = _workspace(_abi.OP_ROTATE, T, N, pad, dev)
-    g = _geom(T, N, pad)
+    g = _geom(T, N, pad, _flags(keep_padded, check_finite))
     lib = _abi.load()
     _abi.check(lib.graphic_rotate(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(out), _ptr(th),
                                   _ptr(fl), _ptr(ws), n, _stream(dev)), "graphic_rotate")
     return (out, fl) if flux else out
 
 
-def median(stack, out=None):
+def median(stack, out=None, check_finite=False):
     """Exact per-pixel float32 median over axis 0 of a [T, N, N] stack."""
     import torch
     T, N = _check_cube(stack, "stack")
     out = torch.empty((N, N), dtype=torch.float32, device=stack.device) if out is None else out
-    g = _geom(T, N, 0)
+    _check_out(out, (N, N), stack.device)
+    g = _geom(T, N, 0, _flags(False, check_finite))
     lib = _abi.load()
     _abi.check(lib.graphic_median(context(stack.device.index or 0), ctypes.byref(g), _ptr(stack), _ptr(out),
                                   None, 0, _stream(stack.device)), "graphic_median")
     return out
 
 
-def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, workspace=None, stream=None):
+def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, workspace=None, stream=None,
+               check_finite=False):
     """Classical ADI: recentre, median PSF, subtract, derotate by -parang,
     median combine.  Returns the final image, plus the PSF and the derotated
     residual cube when asked."""
@@ -145,7 +182,7 @@ def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, w
         ws, n = _workspace(_abi.OP_ADI, T, N, pad, dev)
     else:
         ws, n = workspace, workspace.numel()
-    g = _geom(T, N, pad)
+    g = _geom(T, N, pad, _flags(False, check_finite))
     lib = _abi.load()
     st = _on_stream(stream, dev, [cube, dx, dy, pa, final, psf_t, res_t, ws])
     _abi.check(lib.graphic_adi_reduce(context(dev.index or 0), ctypes.byref(g), _ptr(cube), _ptr(dx), _ptr(dy),
@@ -160,14 +197,15 @@ def adi_reduce(cube, dx, dy, parang_deg, pad=None, psf=False, residuals=False, w
 
 
 def alpha_min_deg(n_fwhm, fwhm, r_min):
-    """Minimum field rotation (degrees) of the per-frame PSF selection: the
-    chord angle 2 arcsin(n_fwhm * fwhm / (2 r_min)) at which a point at radius
-    r_min has moved by n_fwhm FWHM."""
-    import math
-    x = n_fwhm * fwhm / (2.0 * r_min)
-    if not 0.0 <= x <= 1.0:
-        raise ValueError("n_fwhm * fwhm must lie in [0, 2 r_min]")
-    return math.degrees(2.0 * math.asin(x))
+    """Minimum field rotation (degrees) of the per-frame PSF selection, from
+    the library (graphic_alpha_min_deg: the chord angle at which a point at
+    radius r_min has moved by n_fwhm FWHM)."""
+    out = ctypes.c_double()
+    st = _abi.load().graphic_alpha_min_deg(float(n_fwhm), float(fwhm), float(r_min), ctypes.byref(out))
+    if st != _abi.OK:
+        raise ValueError("alpha_min_deg: n_fwhm * fwhm must lie in [0, 2 r_min] with r_min > 0 (%s)"
+                         % _abi.status_string(st))
+    return out.value
 
 
 def median_window(stack, times, parang_deg, t_max, alpha_min, psf=True, resid=False, inplace=False):
@@ -232,16 +270,17 @@ def parallactic_angles(lst_s, ra_deg, dec_deg, lat_deg, device=None):
     return out
 
 
-REGISTER_COLUMNS = ("cx", "cy", "x0", "y0", "i0", "alpha", "beta", "bg", "cost")
+REGISTER_COLUMNS = ("cx", "cy", "x0", "y0", "i0", "alpha", "beta", "bg", "cost", "fwhm", "dx", "dy")
 
 
 def register(cube, threshold, min_size, max_size, half=16, saturation=float("inf"), max_iter=200):
     """Star centroid and Moffat fit of every frame.  Returns a dict of float64
-    [T] tensors (REGISTER_COLUMNS plus fwhm, dx, dy) and int32 flags."""
+    [T] tensors (REGISTER_COLUMNS: centroid, fit parameters, final cost, FWHM
+    and recentring shift, all computed by the library) and int32 flags."""
     import torch
     T, N = _check_cube(cube)
     dev = cube.device
-    out = torch.empty((T, 9), dtype=torch.float64, device=dev)
+    out = torch.empty((T, len(REGISTER_COLUMNS)), dtype=torch.float64, device=dev)
     flags = torch.empty(T, dtype=torch.int32, device=dev)
     prm = _abi.RegisterParams(float(threshold), int(min_size), int(max_size), int(half), int(max_iter),
                               float(saturation))
@@ -249,9 +288,6 @@ def register(cube, threshold, min_size, max_size, half=16, saturation=float("inf
     _abi.check(_abi.load().graphic_register(context(dev.index or 0), ctypes.byref(g), _ptr(cube), ctypes.byref(prm),
                                             _ptr(out), _ptr(flags), _stream(dev)), "graphic_register")
     res = {k: out[:, i] for i, k in enumerate(REGISTER_COLUMNS)}
-    res["fwhm"] = 2.0 * res["alpha"] * torch.sqrt(torch.pow(2.0, 1.0 / res["beta"]) - 1.0)
-    res["dx"] = N / 2.0 - res["x0"]
-    res["dy"] = N / 2.0 - res["y0"]
     res["flags"] = flags
     return res
 
@@ -261,6 +297,7 @@ def median_nan(stack, out=None):
     import torch
     T, N = _check_cube(stack, "stack")
     out = torch.empty((N, N), dtype=torch.float32, device=stack.device) if out is None else out
+    _check_out(out, (N, N), stack.device)
     g = _geom(T, N, 0)
     _abi.check(_abi.load().graphic_median_nan(context(stack.device.index or 0), ctypes.byref(g), _ptr(stack),
                                               _ptr(out), _stream(stack.device)), "graphic_median_nan")
@@ -325,7 +362,7 @@ def badpix_fix(cube, bad_map=None, max_passes=64):
 def annular_rms(a, b=None, width=1.0, n_rings=None, centre=None):
     """RMS of a - b (or of a) in annuli of `width` px around `centre` (x, y;
     default (N/2, N/2)) for every frame of a [T, N, N] (or [N, N]) tensor,
-    the image-quality measure of Sect. 4.  Returns (rms [T, n_rings] or
+    the image-quality measure of Sect. 4.1.  Returns (rms [T, n_rings] or
     [n_rings] float64, counts [n_rings] int64), both on the device; n_rings
     defaults to the annuli that reach the frame corners."""
     import math

@@ -2,6 +2,7 @@
 symbol, and its host-only queries validate geometry (no GPU needed)."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -32,8 +33,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings_and_version(lib):
-    for s in range(6):
+    for s in range(7):
         assert lib.graphic_status_string(s).startswith(b"GRAPHIC")
+    assert b"NONFINITE" in lib.graphic_status_string(_abi.ERR_NONFINITE)
     assert b"gfx950" in lib.graphic_version()
 
 
@@ -61,8 +63,11 @@ def test_workspace_sizes(lib):
         _abi.ERR_UNSUPPORTED
     bad = _abi.Geom(16, 7, 0, 0)
     assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(bad), ctypes.byref(sz)) == _abi.ERR_ARG
-    flags = _abi.Geom(16, 8, 0, 1)
-    assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(flags), ctypes.byref(sz)) == _abi.ERR_ARG
+    for fl in (_abi.KEEP_PADDED, _abi.CHECK_FINITE, _abi.KEEP_PADDED | _abi.CHECK_FINITE):
+        flags = _abi.Geom(16, 8, 0, fl)
+        assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(flags), ctypes.byref(sz)) == _abi.OK
+    unknown = _abi.Geom(16, 8, 0, 4)
+    assert lib.graphic_workspace_size(None, _abi.OP_SHIFT, ctypes.byref(unknown), ctypes.byref(sz)) == _abi.ERR_ARG
     assert lib.graphic_workspace_size(None, 99, ctypes.byref(g), ctypes.byref(sz)) == _abi.ERR_ARG
 
 
@@ -109,3 +114,42 @@ def test_preprocess_and_register_reject_bad_arguments(lib):
     assert sz.value >= 256 * 256 * 4
     assert lib.graphic_workspace_size(None, _abi.OP_BADPIX_FIX, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
     assert sz.value >= 2 * 8 * 8 * 4
+
+
+@pytest.mark.parametrize("n_fwhm,fwhm,r_min", [(1.0, 4.0, 10.0), (1.5, 4.0, 25.0), (0.0, 4.0, 3.0), (2.0, 5.0, 5.0)])
+def test_alpha_min_chord_angle(lib, n_fwhm, fwhm, r_min):
+    """graphic_alpha_min_deg: the chord of the arc that a point at radius
+    r_min sweeps through alpha_min has length n_fwhm * fwhm."""
+    out = ctypes.c_double()
+    assert lib.graphic_alpha_min_deg(n_fwhm, fwhm, r_min, ctypes.byref(out)) == _abi.OK
+    chord = 2.0 * r_min * math.sin(math.radians(out.value) / 2.0)
+    assert abs(chord - n_fwhm * fwhm) <= 1e-12 * max(1.0, n_fwhm * fwhm)
+    assert 0.0 <= out.value <= 180.0
+
+
+def test_alpha_min_rejects_impossible_chords(lib):
+    out = ctypes.c_double()
+    for args in ((3.0, 4.0, 5.0), (-1.0, 4.0, 10.0), (1.0, 4.0, 0.0), (1.0, float("nan"), 10.0),
+                 (1.0, float("inf"), 10.0)):
+        assert lib.graphic_alpha_min_deg(*args, ctypes.byref(out)) == _abi.ERR_ARG
+    assert lib.graphic_alpha_min_deg(1.0, 4.0, 10.0, None) == _abi.ERR_ARG
+
+
+def test_output_tensor_checks():
+    """Caller-supplied outputs must match the result exactly (shape, dtype,
+    contiguity, device) before any pointer reaches the library."""
+    import torch
+    from paper_1510_04331_amd import ops
+    dev = torch.device("cpu")
+    good = torch.empty((3, 8, 8), dtype=torch.float32)
+    assert ops._check_out(good, (3, 8, 8), dev) is good
+    for bad in (torch.empty((2, 8, 8)), torch.empty((3, 8, 6)), torch.empty((3, 8, 8), dtype=torch.float64),
+                torch.empty((3, 8, 16))[:, :, ::2], torch.empty(192)):
+        with pytest.raises(ValueError):
+            ops._check_out(bad, (3, 8, 8), dev)
+    with pytest.raises(ValueError):
+        ops._check_out(good, (3, 8, 8), torch.device("cuda", 0))
+    with pytest.raises(ValueError):
+        ops._check_out(torch.empty((8, 8)), (3, 8, 8), dev)
+    with pytest.raises(ValueError):
+        ops._check_out(None, (8, 8), dev)

@@ -53,20 +53,30 @@ def test_nominal_flops_per_frame():
     assert bench.alg_flops_per_frame("median", N, P) is None
 
 
-def test_peaks_are_the_published_ones():
+def test_peaks():
+    """The published MI355X peaks, and the derived non-packed FP32 rate."""
     assert bench.HBM_PEAK_GBS == 8000.0
-    # FP32 vector, no packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-    assert round(bench.ALU_PEAK_TFLOPS, 1) == 78.6
+    assert bench.FP32_PEAK_TFLOPS == 157.3
+    # derived: FP32 vector without packed instructions, 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+    assert round(bench.FP32_NONPACKED_TFLOPS, 1) == 78.6
 
 
-def test_roofline_of_a_line_pass_and_of_the_median():
-    r = bench.roofline({"achieved_GBps": 2170.0, "achieved_TFLOPs": 29.84}, "shear_y", 12345)
-    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["kernel"] == "shear_y"
-    assert r["peak"] == 78.6 and r["traffic"] == 12345
-    assert abs(r["frac"] - 29.84 / bench.ALU_PEAK_TFLOPS) < 1e-4
-    assert abs(r["hbm_frac"] - 2170.0 / 8000.0) < 1e-4
-    m = bench.roofline({"achieved_GBps": 4761.0}, "median", None)
-    assert m["bound"] == "hbm" and m["unit"] == "GB/s" and m["peak"] == 8000.0
+def test_roofline_is_hbm_over_algorithmic_bytes():
+    """frac = algorithmic bytes per launch / mean launch time / 8 TB/s; the
+    line passes' nominal FFT rate is reported beside it."""
+    alg = 512 * 16 * 1024 * 1024          # shear_y of a 512-frame chunk at 1024^2 (16 N^2 per frame)
+    ms = 3.926
+    gbps = alg / (ms * 1e-3) / 1e9
+    r = bench.roofline({"achieved_GBps": gbps, "achieved_TFLOPs": 29.84, "alg_bytes_per_launch": alg,
+                        "avg_launch_ms": ms}, "shear_y", 12345)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["kernel"] == "shear_y"
+    assert r["peak"] == 8000.0 and r["traffic"] == 12345
+    assert abs(r["frac"] - 0.2735) < 1e-3
+    assert abs(r["alu"]["frac_published"] - 29.84 / 157.3) < 1e-4
+    assert abs(r["alu"]["frac_nonpacked"] - 29.84 / bench.FP32_NONPACKED_TFLOPS) < 1e-4
+    m = bench.roofline({"achieved_GBps": 4761.0, "alg_bytes_per_launch": 1e9, "avg_launch_ms": 0.21}, "median",
+                       None)
+    assert m["bound"] == "hbm" and m["unit"] == "GB/s" and m["peak"] == 8000.0 and "alu" not in m
     assert abs(m["frac"] - 4761.0 / 8000.0) < 1e-4 and m["traffic"] is None
 
 

@@ -76,7 +76,7 @@ def test_shift_parity(torch_dev, T, N, pad):
         assert abs(got[t].astype(np.float64).sum() - ref.sum()) <= FLUX * np.abs(cube[t]).sum()
 
 
-ROT_ANGLES = [0.0, 11.3, -30.0, 45.0, 90.0, -90.0, 135.0, -170.0, 180.0, 0.7]
+ROT_ANGLES = [0.0, 11.3, -30.0, 45.0, 90.0, -90.0, 135.0, -170.0, 180.0, 0.7, 350.0, 360.0, -300.0, 539.0]
 
 
 @pytest.mark.parametrize("N,pad", [(8, 0), (6, 0), (64, 0), (64, 64), (40, 256), (128, 0)])

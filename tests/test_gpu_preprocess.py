@@ -1,4 +1,4 @@
-"""GPU: image pre-processing (Sect. 3.1-3.2) against the oracle, bit for
+"""GPU: image pre-processing (Sect. 3.2) against the oracle, bit for
 bit: star masks, the NaN-aware master-sky median, nearest-sky subtraction,
 the sigma-clipped bad pixel map (median exact, sigma to rounding) and the
 neighbour repair passes."""

@@ -1,4 +1,4 @@
-"""GPU: the image-quality test of Sect. 4 against the oracle.
+"""GPU: the image-quality test of Sect. 4.1 against the oracle.
 
 The annular RMS has the oracle's pixel counts exactly and its float64 RMS to
 rounding (the GPU adds the squares in atomics' order).  The round trips of

@@ -1,4 +1,4 @@
-"""GPU: registration (Sect. 2) against the oracle.
+"""GPU: registration (Sect. 3.1) against the oracle.
 
 Parallactic angles agree to rounding (different math libraries).  The
 centroid is the same weighted mean of the same pixels (float64 sums in another
@@ -44,6 +44,9 @@ def _check(got, ref, i):
     for k in ("i0", "alpha", "beta"):
         assert abs(got[k][i] - ref[k][i]) <= 1e-6 * abs(ref[k][i]), (i, k, got[k][i], ref[k][i])
     assert abs(got["bg"][i] - ref["bg"][i]) <= 1e-6 * max(1.0, abs(ref["bg"][i])), i
+    # the library's FWHM (Sect. 3.1.2) and recentring shift against the oracle's
+    assert abs(got["fwhm"][i] - ref["fwhm"][i]) <= 2e-6 * abs(ref["fwhm"][i]), (i, got["fwhm"][i], ref["fwhm"][i])
+    assert abs(got["dx"][i] - ref["dx"][i]) < 1e-6 and abs(got["dy"][i] - ref["dy"][i]) < 1e-6, i
 
 
 def _host(res):

@@ -157,7 +157,7 @@ def test_rotate_half_turn_is_point_reflection(theta):
     np.testing.assert_allclose(out, ref, atol=1e-12)
 
 
-@pytest.mark.parametrize("theta", [30.0, -45.0, 60.0, 120.0, -150.0])
+@pytest.mark.parametrize("theta", [30.0, -45.0, 60.0, 120.0, -150.0, 350.0, -300.0, 420.0, 710.0])
 def test_rotated_gaussian_closed_form(theta):
     """A Gaussian at c + p0 ends at c + R_theta p0, counter-clockwise in the
     (x right, y up) frame (rotation sign, shear order, centre)."""
@@ -170,6 +170,24 @@ def test_rotated_gaussian_closed_form(theta):
     q = (math.cos(a) * p0[0] - math.sin(a) * p0[1], math.sin(a) * p0[0] + math.cos(a) * p0[1])
     ref = _blobs(n, [(c + q[0], c + q[1])], sigma=3.0)
     np.testing.assert_allclose(out, ref, atol=1e-9)
+
+
+@pytest.mark.parametrize("theta", [0.0, 11.3, -30.0, 135.0, -170.0, 89.0])
+def test_rotation_is_periodic_in_360_degrees(theta):
+    """R_theta has period 360 deg, so theta + 360 k turns the frame like theta
+    (a missing angle reduction sends tan(theta/2) toward infinity and wraps
+    the shears round the padded frame)."""
+    f = _blobs(48, [(30.0, 20.0), (18.0, 27.0)], sigma=3.0, amps=[1.0, -0.5])
+    ref = O.rotate(f, theta)
+    for k in (1, -1, 2, -3):
+        np.testing.assert_allclose(O.rotate(f, theta + 360.0 * k), ref, atol=1e-10)
+
+
+def test_full_turn_is_identity():
+    """theta = 360 deg and -720 deg leave the frame as it is."""
+    f = np.random.default_rng(12).normal(size=(20, 20))
+    np.testing.assert_allclose(O.rotate(f, 360.0), f, atol=1e-13)
+    np.testing.assert_allclose(O.rotate(f, -720.0), f, atol=1e-13)
 
 
 def test_double_rotation_recovers_input(golden):

@@ -1,4 +1,4 @@
-"""Pins of the pre-processing oracle (Sect. 3.1-3.2): star mask, NaN-aware
+"""Pins of the pre-processing oracle (Sect. 3.2): star mask, NaN-aware
 median, nearest sky, sigma-clipped bad pixel map and neighbour repair."""
 
 import numpy as np

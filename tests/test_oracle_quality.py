@@ -1,4 +1,4 @@
-"""CPU pins of the image-quality oracle (Sect. 4: double shift and double
+"""CPU pins of the image-quality oracle (Sect. 4.1: double shift and double
 rotation, residual RMS in annuli).  Each test checks the oracle against a fact
 from outside it: lattice-point counts of the sum-of-two-squares function,
 closed-form ring averages, exact round trips of band-limited blobs, and the

@@ -1,4 +1,4 @@
-"""Pins of the registration oracle (Sect. 2): parallactic angle against
+"""Pins of the registration oracle (Sect. 3.1): parallactic angle against
 spherical-trigonometry identities, centroid against symmetric blobs and the
 patch rules, Moffat fit against noiseless images of known parameters."""
 
