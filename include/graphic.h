@@ -171,6 +171,33 @@ graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom,
                               void* ws, size_t ws_bytes, graphic_stream stream);
 
 /*
+ * graphic_rotate without a workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  It makes no hipMalloc, hipFree or other
+ * allocating call (and creates no timing events).  Its scratch -- the
+ * per-frame shear factors, the half-turn list and a chunk of x-sheared
+ * frames -- is a library-owned static device array of
+ * GRAPHIC_NOALLOC_SCRATCH_BYTES (128 MiB) on each GPU the library runs on,
+ * held until the process ends; its address on a device is taken once, when
+ * the first context is created on that device.
+ *   Arguments, results and geom flags as graphic_rotate (GRAPHIC_KEEP_PADDED
+ *   is allowed; GRAPHIC_CHECK_FINITE, which synchronises, is not).
+ *   Limit: about 24 T bytes of parameters plus one N x P float32 frame must
+ *   fit the array, else GRAPHIC_ERR_UNSUPPORTED (checked first, nothing
+ *   launched); the frames run in chunks of as many as fit.
+ *   Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind (nothing in it needs to start at zero): calls that overlap on
+ *   one device -- other streams, host threads or contexts -- race on it and
+ *   must be ordered by the caller.  GRAPHIC_ERR_HIP if the array's address
+ *   could not be taken on this device.
+ */
+#define GRAPHIC_NOALLOC_SCRATCH_BYTES (128u << 20)
+graphic_status graphic_rotate_noalloc(graphic_ctx ctx, const graphic_geom* geom,
+                                      const float* in, float* out,
+                                      const double* theta_deg, double* flux,
+                                      graphic_stream stream);
+
+/*
  * Exact per-pixel median over the T frames of a float32 stack (the combiner
  * of Sect. 3.3 and 3.4).  Values are ordered by IEEE totalOrder (-0 < +0);
  * with lo and hi the elements of rank (T-1)/2 and T/2, the result is

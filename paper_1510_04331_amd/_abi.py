@@ -20,7 +20,7 @@ KEEP_PADDED, CHECK_FINITE = 1, 2
 # every symbol that include/graphic.h declares
 EXPORTS = (
     "graphic_create", "graphic_destroy", "graphic_status_string", "graphic_version",
-    "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate",
+    "graphic_resolved_pad", "graphic_workspace_size", "graphic_shift", "graphic_rotate", "graphic_rotate_noalloc",
     "graphic_median", "graphic_adi_reduce", "graphic_median_window", "graphic_alpha_min_deg",
     "graphic_adi_reduce_window",
     "graphic_parallactic_angles", "graphic_register", "graphic_median_nan", "graphic_mask_disk",
@@ -87,6 +87,8 @@ def load():
     lib.graphic_shift.restype = st
     lib.graphic_rotate.argtypes = [vp, g, vp, vp, vp, vp, vp, sz, vp]
     lib.graphic_rotate.restype = st
+    lib.graphic_rotate_noalloc.argtypes = [vp, g, vp, vp, vp, vp, vp]
+    lib.graphic_rotate_noalloc.restype = st
     lib.graphic_median.argtypes = [vp, g, vp, vp, vp, sz, vp]
     lib.graphic_median.restype = st
     lib.graphic_adi_reduce.argtypes = [vp, g, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -346,7 +347,12 @@ graphic_status do_shift_batch(graphic_ctx ctx, int N, int P, const ShiftItem* it
 graphic_status do_rotate_batch(graphic_ctx ctx, int N, int P, const RotItem* it, int n, double sign, void* ws,
                                size_t ws_bytes, hipStream_t st, bool tm = false) {
   long long F = 0;
-  std::vector<long long> start(n + 1, 0);
+  // cube start frames (a small batch keeps them on the stack, so that a
+  // single-cube rotation makes no allocation at all)
+  long long start_small[kMaxCubesPerLaunch + 1];
+  std::vector<long long> start_big;
+  if (n > kMaxCubesPerLaunch) start_big.assign(n + 1, 0);
+  long long* start = n > kMaxCubesPerLaunch ? start_big.data() : start_small;
   for (int i = 0; i < n; ++i) {
     start[i] = F;
     F += it[i].T;
@@ -800,6 +806,43 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
 }  // namespace
 
 // ===========================================================================
+// Static scratch of graphic_rotate_noalloc
+// ===========================================================================
+// One array per GPU that the library runs on, held until the process ends.
+// In host code its name is only a stand-in for the device variable: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device (with that device current) when a context is created on
+// it, and only that address is handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the calling device's copy of `scratch` (device `dev` is current).
+hipError_t resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+// ===========================================================================
 // Public entry points
 // ===========================================================================
 extern "C" {
@@ -846,6 +889,9 @@ graphic_status graphic_create(graphic_ctx* out, int hip_device) {
     graphic_destroy(c);
     return s;
   }
+  // the no-allocation entry point's scratch on this device (its failure only
+  // disables that entry point, which then returns GRAPHIC_ERR_HIP)
+  (void)resolve_scratch(hip_device);
   *out = c;
   return GRAPHIC_OK;
 }
@@ -963,6 +1009,41 @@ graphic_status graphic_rotate(graphic_ctx ctx, const graphic_geom* geom, const f
   }
   if (flux && (s = do_sums(ctx, T, No, out, flux, 1, st)) != GRAPHIC_OK) return s;
   return GRAPHIC_OK;
+}
+
+graphic_status graphic_rotate_noalloc(graphic_ctx ctx, const graphic_geom* geom, const float* in, float* out,
+                                      const double* theta_deg, double* flux, graphic_stream stream) {
+  int P = 0;
+  if (!ctx) return GRAPHIC_ERR_ARG;
+  graphic_status s = check_geom(geom, &P, GRAPHIC_KEEP_PADDED);
+  if (s != GRAPHIC_OK) return s;
+  const long long T = geom->n_frames;
+  const int N = geom->n;
+  // the static scratch must hold the per-frame parameters and one working frame
+  const RotLayout need = rot_layout(T, N, P, ctx->chunk_bytes, 0);
+  if (need.params + align_up((size_t)N * P * sizeof(float)) > kNoAllocScratchBytes) return GRAPHIC_ERR_UNSUPPORTED;
+  if (!in || !out || !theta_deg) return GRAPHIC_ERR_ARG;
+  const bool padded = (geom->flags & GRAPHIC_KEEP_PADDED) != 0;
+  if (padded ? padded_overlap_bad(in, out, T, N, P) : overlap_bad(in, out, (size_t)T * N * N * sizeof(float)))
+    return GRAPHIC_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
+  void* ws = scratch_ptr(ctx->device);
+  if (!ws) return GRAPHIC_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool timing = ctx->timing;        // event timing would create events: off for this call
+  ctx->timing = false;
+  if (flux) s = do_sums(ctx, T, N, in, flux, 0, st);
+  if (s == GRAPHIC_OK) {
+    if (padded) {
+      s = do_rotate_padded(ctx, N, P, T, in, out, theta_deg, ws, kNoAllocScratchBytes, st);
+    } else {
+      const RotItem item{in, out, T, theta_deg};
+      s = do_rotate_batch(ctx, N, P, &item, 1, 1.0, ws, kNoAllocScratchBytes, st);
+    }
+  }
+  if (s == GRAPHIC_OK && flux) s = do_sums(ctx, T, padded ? P : N, out, flux, 1, st);
+  ctx->timing = timing;
+  return s;
 }
 
 graphic_status graphic_median(graphic_ctx ctx, const graphic_geom* geom, const float* stack, float* out,
