@@ -202,7 +202,9 @@ graphic_status graphic_rotate_noalloc(graphic_ctx ctx, const graphic_geom* geom,
  * of Sect. 3.3 and 3.4).  Values are ordered by IEEE totalOrder (-0 < +0);
  * with lo and hi the elements of rank (T-1)/2 and T/2, the result is
  * (lo + hi) * 0.5 in float32, which is lo when T is odd.  NaN input is a
- * precondition violation.
+ * precondition violation.  T <= 2^24: up to 4096 frames each pixel's values
+ * are read once into registers; deeper stacks are read once per 8-bit digit
+ * of the select (four to six passes over the stack).
  *   stack : [T][N][N] float32 (only T and N of geom are used).
  *   out   : [N][N] float32.
  *   ws    : graphic_workspace_size(GRAPHIC_OP_MEDIAN) bytes (may be 0; then ws may be NULL).
@@ -402,7 +404,7 @@ graphic_status graphic_annular_rms(graphic_ctx ctx, const graphic_geom* geom, co
 
 typedef struct {
     const float* cube;          /* [T][N][N] float32 */
-    int64_t n_frames;           /* T, 1 <= T <= 4096 */
+    int64_t n_frames;           /* T, 1 <= T <= 2^24 */
     int32_t n, pad;             /* N and P as in graphic_geom */
     const double* dx;           /* [T] recentring shifts */
     const double* dy;           /* [T] */

@@ -36,7 +36,12 @@ using namespace graphic;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxT_Median = 4096;
+// Frame counts: up to 4096 frames a pixel's values stay in registers (one
+// read of the stack); deeper stacks take the streaming select (one read per
+// digit), up to 2^24 frames.  The NaN-ignoring median keeps the register form.
+constexpr long long kMaxT_Median = 1LL << 24;
+constexpr int kMaxT_RegisterMedian = 4096;
+constexpr int kMaxT_NanMedian = 4096;
 constexpr int kMaxT_Window = 2048;      // the per-frame median keeps a median per held frame in registers
 constexpr size_t kDefaultChunkBytes = size_t(4) << 30;   // rotation scratch per chunk (fewer, fuller launches)
 
@@ -113,10 +118,37 @@ void host_tables(int M, std::vector<float2>& fwd, std::vector<float2>& inv, std:
   }
 }
 
+// Table of the two-wave jobs at M = 2048 (Ma = 32, Mb = 64, P = 4096):
+// split[((h*2 + e)*Ma + j)*Ma + n1] = exp(-2 pi i (h (n1 + Ma j) / P + j e / Mb)).
+constexpr int kSplitTabM = 2048, kSplitTabMa = 32, kSplitTabMb = 64;
+constexpr size_t kSplitTabN = (size_t)4 * kSplitTabMa * kSplitTabMa;
+
+void host_split_table(std::vector<float2>& t) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const int Ma = kSplitTabMa, Mb = kSplitTabMb, P = 2 * kSplitTabM;
+  t.assign(kSplitTabN, float2{0, 0});
+  for (int h = 0; h < 2; ++h)
+    for (int e = 0; e < 2; ++e)
+      for (int j = 0; j < Ma; ++j)
+        for (int n1 = 0; n1 < Ma; ++n1) {
+          // phase in turns, reduced exactly in integers: h (n1 + Ma j) / P + j e / Mb
+          const long num = (long)h * (n1 + Ma * j) + (long)j * e * (P / Mb);
+          const double a = two_pi * (double)(num % P) / P;
+          t[((h * 2 + e) * Ma + j) * Ma + n1] = float2{(float)std::cos(a), (float)-std::sin(a)};
+        }
+}
+
 graphic_status build_tables(graphic_ctx ctx) {
   size_t total = 0;
   for (int M = kMinM; M <= kMaxM; M *= 2) total += (size_t)4 * M * sizeof(float2);
+  const size_t split_off = total / sizeof(float2);
+  total += kSplitTabN * sizeof(float2);
   std::vector<float2> host(total / sizeof(float2));
+  {
+    std::vector<float2> st;
+    host_split_table(st);
+    std::memcpy(&host[split_off], st.data(), kSplitTabN * sizeof(float2));
+  }
   size_t off = 0;
   std::vector<size_t> offs;
   for (int M = kMinM; M <= kMaxM; M *= 2) {
@@ -138,6 +170,7 @@ graphic_status build_tables(graphic_ctx ctx) {
     t.fwd = base;
     t.inv = base + M;
     t.fold = base + 2 * M;
+    t.split = M == kSplitTabM ? static_cast<const float2*>(ctx->tables) + split_off : nullptr;
   }
   return GRAPHIC_OK;
 }
@@ -247,7 +280,11 @@ int col_variant(graphic_ctx ctx, int P, int mirror) {
   return v < 0 ? 0 : v;
 }
 
-int median_class(long long T) { return ilog2((int)((T + 63) / 64)) & 7; }
+// Tuning class of a frame count: log2 of the median's values per thread
+// (0 .. 6 for the register form; 7 for the streaming select, which has no variants).
+int median_class(long long T) {
+  return T > kMaxT_RegisterMedian ? 7 : ilog2((int)((T + 63) / 64));
+}
 
 int median_variant(graphic_ctx ctx, long long T) {
   const int v = ctx->med_var[median_class(T)];
@@ -783,7 +820,8 @@ graphic_status adi_batch(graphic_ctx ctx, const graphic_cube_desc* d, int n, uin
     for (int i : c) {
       sh.push_back(ShiftItem{d[i].cube, stack[i], d[i].n_frames, d[i].dx, d[i].dy});
       rot.push_back(RotItem{stack[i], stack[i], d[i].n_frames, d[i].parang_deg});
-      tm = tm && plan.stack_off[i] != SIZE_MAX && (long long)N * 4 * d[i].n_frames <= 0x7fffffffLL;
+      tm = tm && plan.stack_off[i] != SIZE_MAX && (long long)N * 4 * d[i].n_frames <= 0x7fffffffLL &&
+           d[i].n_frames <= kMaxT_RegisterMedian;
     }
     // S_i = shift(cube_i): every cube of the class in the same launches
     if ((s = do_shift_batch(ctx, N, P, sh.data(), (int)sh.size(), st, tm)) != GRAPHIC_OK) return s;
@@ -1234,7 +1272,7 @@ graphic_status graphic_median_nan(graphic_ctx ctx, const graphic_geom* geom, con
                                   graphic_stream stream) {
   if (!ctx || !geom || !stack || !out) return GRAPHIC_ERR_ARG;
   if (geom->n_frames < 1 || geom->n < 1 || geom->flags != 0) return GRAPHIC_ERR_ARG;
-  if (geom->n_frames > kMaxT_Median) return GRAPHIC_ERR_UNSUPPORTED;
+  if (geom->n_frames > kMaxT_NanMedian) return GRAPHIC_ERR_UNSUPPORTED;
   const long long T = geom->n_frames;
   const int N = geom->n;
   if (overlap_bad(stack, out, (size_t)N * N * sizeof(float)) || (out >= stack && out < stack + (size_t)T * N * N))
@@ -1507,7 +1545,10 @@ graphic_status graphic_autotune(graphic_ctx ctx, const graphic_geom* geom, void*
   // median: the pipeline runs it twice per cube, once rewriting the stack as
   // residuals and once read-only; both are timed, on as many pixels of this
   // frame count as the workspace holds
-  long long npix = std::min<long long>((long long)N * N, (long long)(ws_bytes / sizeof(float)) / (T + 1));
+  // (deep stacks take the streaming select, which has no variants)
+  long long npix = T > kMaxT_RegisterMedian
+                       ? 0
+                       : std::min<long long>((long long)N * N, (long long)(ws_bytes / sizeof(float)) / (T + 1));
   npix -= npix % 128;
   if (npix >= std::min<long long>(16384, (long long)N * N - ((long long)N * N) % 128)) {
     float* out = buf + (size_t)T * npix;

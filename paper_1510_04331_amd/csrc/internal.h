@@ -14,10 +14,13 @@ constexpr int kMaxM = 2048;   // largest half working size (P = 4096)
 //   fwd[k2*Ma + n1]  = exp(-2 pi i n1 k2 / M)          (four-step, forward)
 //   inv[n1*Mb + k2]  = exp(+2 pi i n1 k2 / M)          (four-step, inverse)
 //   fold[h*M + m]    = 1 (h = 0) or exp(-2 pi i m / P) (h = 1)
+//   split[((h*2 + e)*Ma + j)*Ma + n1] = exp(-2 pi i (h (n1 + Ma j) / P + j e / Mb))
+//                                     (M = 2048 only: the two-wave jobs)
 struct TwiddleTables {
   const float2* fwd;
   const float2* inv;
   const float2* fold;
+  const float2* split;
 };
 
 constexpr int kMaxCubesPerLaunch = 16;

@@ -170,8 +170,20 @@ constexpr int waves_per_eu() {
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 
+// Cache policy of the frame loads: the x-shears read their frames with the
+// non-temporal hint (each value is read once, and the twiddle tables then
+// stay cached: measured 0.3-0.6 ms faster per 2048 frames of 1024^2); the
+// y-shear, which writes back the lines it reads, and the shift passes were
+// measured slower or unchanged with it and keep the default.
+constexpr int kCpolDefault = 0;
+constexpr int kCpolNonTemporal = 2;
+#ifndef GRAPHIC_PRIO_ALL
+#define GRAPHIC_PRIO_ALL 0
+#endif
+
+template <int CPOL = kCpolDefault>
 __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, int soff = 0) {
-  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
+  return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, CPOL));
 }
 __device__ __forceinline__ cf buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off, int soff) {
   const v2i t = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0);
@@ -360,7 +372,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // Waves issue their input loads at raised priority so that every wave's
   // requests are in flight early; measured per pass: it helps the shift
   // passes and the first shear, and slows the y-shear and the last shear.
-  constexpr bool kLoadPrio = !(KIND == kColPass && MIR) && IO != kIoFullWin;
+  constexpr bool kLoadPrio = GRAPHIC_PRIO_ALL || (!(KIND == kColPass && MIR) && IO != kIoFullWin);
+  constexpr int kLdPol = (KIND == kRowPass && MIR) ? kCpolNonTemporal : kCpolDefault;
   if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(2);
 
   // ---- load, pack and fold into this half's branch ----
@@ -424,7 +437,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const int k = (n2 + Mb / 2) % Mb;
       const int sa = (int)off_src(Ma * k);
       const int sb = (int)off_src(MIR ? Ma * (Mb - 1 - k) : Ma * k);
-      const float av = buf_ld(srcA, la_lane, sa), bv = buf_ld(srcB, lb_lane, sb);
+      const float av = buf_ld<kLdPol>(srcA, la_lane, sa), bv = buf_ld<kLdPol>(srcB, lb_lane, sb);
       const float sc = n2 < Mb / 2 ? sg : 1.0f;    // the valid candidate is n = m + M below Mb/2
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({sc * av, sc * bv}, w);
@@ -438,8 +451,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const int sa0 = (int)off_src(Ma * n2), sa1 = (int)off_src(Ma * n2 + M);
       const int sb0 = (int)off_src(MIR ? Ma * (2 * Mb - 1 - n2) : Ma * n2);
       const int sb1 = (int)off_src(MIR ? Ma * (Mb - 1 - n2) : Ma * n2 + M);
-      const float a0 = buf_ld(srcA, la_lane, sa0), a1 = buf_ld(srcA, la_lane, sa1);
-      const float b0 = buf_ld(srcB, lb_lane, sb0), b1 = buf_ld(srcB, lb_lane, sb1);
+      const float a0 = buf_ld<kLdPol>(srcA, la_lane, sa0), a1 = buf_ld<kLdPol>(srcA, la_lane, sa1);
+      const float b0 = buf_ld<kLdPol>(srcB, lb_lane, sb0), b1 = buf_ld<kLdPol>(srcB, lb_lane, sb1);
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({fmaf(sg, a1, a0), fmaf(sg, b1, b0)}, w);
     }
@@ -457,7 +470,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
         const unsigned pb = (unsigned)(rev_b ? (L - 1 - u) : u);
         const unsigned oa = in ? base_a + off_src((int)pa) : kOOB;
         const unsigned ob = in ? base_b + off_src((int)pb) : kOOB;
-        z[cnd] = {buf_ld(srcA, oa), buf_ld(srcB, ob)};
+        z[cnd] = {buf_ld<kLdPol>(srcA, oa), buf_ld<kLdPol>(srcB, ob)};
       }
       const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
       v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
@@ -672,6 +685,399 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Half size M = 2048 (P = 4096): one job on two waves.
+//
+// With the four-step split M = Ma x Mb = 32 x 64 a one-wave job would hold
+// Mb = 64 complex values per lane, more than the registers of the two waves a
+// SIMD must run to hide latency.  Here wave h of a job holds the even (h = 0)
+// or odd (h = 1) bins, and its 64 lanes are (e, n1): e = lane / 32 splits the
+// 64-point transforms over n2 / k2 into two 32-point halves, so every lane
+// holds 32 values.
+//   * forward, decimation in frequency over n2 = j + 32 s: lane e forms
+//     (t_0 + (-1)^e t_1) W_64^(j e) from the two folded inputs of s = 0, 1
+//     (it loads both), then a 32-point transform gives the bins k2 = 2k + e;
+//     the fold twiddle of the odd half and W_64^(j e) are one table factor;
+//   * step C as in process_block, one k2 row per lane;
+//   * inverse, decimation in time over k2 = 2k + e: 32-point inverse
+//     transforms give Y_e[j]; each value is scaled by the conjugate table
+//     factor, the two e halves are combined with a lane swap across the 32-lane
+//     halves (permlane32_swap), and the two h waves through LDS: with
+//     A, B (wave 0) and C, D (wave 1) the scaled values, P0 = A + B,
+//     M0 = A - B, P1 = C + D, M1 = C - D, the outputs at m + 1024 q of the
+//     padded line (m = n1 + 32 j) are P0 + P1, M0 + i M1, P0 - P1, M0 - i M1
+//     for q = 0 .. 3.
+// Canonical index patterns only (window or whole line in, window or whole
+// line out); half-turned frames and other geometries take process_block.
+// ---------------------------------------------------------------------------
+constexpr int kSplitM = 2048;
+constexpr int kSplitMa = 32, kSplitMb = 64;
+constexpr int kSplitRowp = kSplitMa + 1;                 // padded LDS row (floats)
+constexpr int kSplitHalf = kSplitMb * kSplitRowp;        // floats of one wave's exchange area
+constexpr int kSplitJobF = 2 * kSplitHalf;               // floats of a job's exchange areas
+
+template <int KIND, int G, bool STG>
+constexpr int split_lds_floats() {
+  constexpr int ex = G * kSplitJobF;
+  constexpr int stg = STG ? kSplitM * (2 * G + 1) : 0;
+  return (ex > stg ? ex : stg) + G * 2 * 2 * kSplitMa;   // + per-wave phasor tables
+}
+
+// e ? b : a for a lane-dependent e, on both parts.
+__device__ __forceinline__ cf csel(bool e, cf a, cf b) { return {e ? b.x : a.x, e ? b.y : a.y}; }
+
+template <int KIND, int G, int IO, bool MIR, bool STG>
+__device__ __forceinline__ void process_block_split(const LinePass& p, const unsigned f, const unsigned jb) {
+  constexpr int M = kSplitM, Ma = kSplitMa, Mb = kSplitMb, ROWP = kSplitRowp;
+  constexpr int P = 2 * M;
+  constexpr int NT = G * 128;                            // threads of the block
+  static_assert(IO == kIoWinWin || IO == kIoWinFull || IO == kIoFullWin, "canonical index patterns");
+  static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
+  static_assert(KIND == kColPass ? STG : G == 1, "row passes: one job per block");
+  extern __shared__ float lds_raw[];
+  const int tid = threadIdx.x;
+  const int jl = __builtin_amdgcn_readfirstlane(tid >> 7);          // job of the block
+  const int h = __builtin_amdgcn_readfirstlane((tid >> 6) & 1);     // wave of the job: even / odd bins
+  const int lane = tid & 63;
+  const int e = lane >> 5;                               // half of the 64-point transforms
+  const int n1 = lane & 31;
+  float* xa = lds_raw + jl * kSplitJobF + h * kSplitHalf;          // this wave's exchange area
+  float* xo = lds_raw + jl * kSplitJobF + (1 - h) * kSplitHalf;    // the other wave's
+  constexpr int kPtab = split_lds_floats<KIND, G, STG>() - G * 2 * 2 * Ma;
+  cf* ptab = reinterpret_cast<cf*>(lds_raw + kPtab) + (jl * 2 + h) * Ma;
+  float* stg = lds_raw;
+  constexpr int SP = 2 * G + 1;
+
+  const int j = (int)jb * G + jl;
+  const bool job_ok = j < p.n_jobs;
+  const int c = P / 2;
+  const int line_lo = p.line_lo;
+  int la, lb2;
+  bool b_exists = true;
+  if (MIR) {
+    la = c - j;
+    lb2 = (c + j) & (P - 1);
+    b_exists = (j != 0) && (lb2 != la);
+  } else {
+    la = line_lo + 2 * j;
+    lb2 = la + 1;
+  }
+  const int ra = (la - line_lo + P) & (P - 1);
+  const int rb = (lb2 - line_lo + P) & (P - 1);
+  const bool a_ok = job_ok && ra < p.n_lines;
+  const bool b_ok = job_ok && b_exists && rb < p.n_lines;
+  const float* src_base = p.src;
+  float* dst_base = p.dst;
+  const double* sh0 = p.sh0;
+  long long fsrc = f, fdst = f, fsh = f;
+  if (p.n_cubes > 0) {
+    int ci = 0;
+    for (int q2 = 1; q2 < p.n_cubes; ++q2)
+      if ((long long)f >= p.cubes[q2].frame0) ci = q2;
+    const long long fl = (long long)f - p.cubes[ci].frame0;
+    if (p.cubes[ci].src) { src_base = p.cubes[ci].src; fsrc = fl; }
+    if (p.cubes[ci].dst) { dst_base = p.cubes[ci].dst; fdst = fl; }
+    if (p.cubes[ci].sh0) { sh0 = p.cubes[ci].sh0; fsh = fl; }
+  }
+  double sft = 0.0;
+  if (sh0) sft += sh0[fsh];
+  if (p.sh1) sft += p.sh1[f] * (double)(la - c);
+  const double q = sft / (double)P;
+
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(src_base + (size_t)fsrc * p.src_fs, (unsigned)p.src_fs * 4u);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc(dst_base + (size_t)fdst * p.dst_fs, (unsigned)p.dst_fs * 4u);
+  const __amdgpu_buffer_rsrc_t tsplit = make_rsrc(p.tw.split, 4u * Ma * Ma * 8u);
+  const __amdgpu_buffer_rsrc_t tfwd = make_rsrc(p.tw.fwd, (unsigned)M * 8u);
+  const __amdgpu_buffer_rsrc_t tinv = make_rsrc(p.tw.inv, (unsigned)M * 8u);
+  const unsigned ls4 = (unsigned)p.src_ls * 4u;
+  const int ps4 = p.src_ps * 4;
+  // per-lane table row of (h, e, n1): entry j at + j * Ma
+  const unsigned tw_lane = (unsigned)(((h * 2 + e) * Ma) * Ma + n1) * 8u;
+
+  // per-wave phasor table over k1
+  if (e == 0) {
+    const int k1s = n1 < Ma / 2 ? n1 : n1 - Ma;
+    ptab[n1] = phase_exp((double)(2 * Mb) * (double)k1s, q, 1.0f / (float)P);
+  }
+
+  // ---- load and fold: a_e[j] = T[h][e][n1][j] * ((-1)^h z_s0 + (-1)^e (-i)^h z_s1) for a window
+  // input (z_s0 at window position m + 1024, z_s1 at m, m = n1 + 32 j), or with
+  // z_s = z[m + 1024 s] + (-1)^h z[m + 1024 s + 2048] for a whole-line input ----
+  const float sgn_h = h ? -1.0f : 1.0f;
+  const float sgn_e = e ? -1.0f : 1.0f;
+  // (-1)^e (-i)^h z_s1 as a select: h = 0: sgn_e z; h = 1: sgn_e (z.y, -z.x)
+  auto rot = [&](cf z) -> cf { return h ? cf{sgn_e * z.y, -sgn_e * z.x} : cf{sgn_e * z.x, sgn_e * z.y}; };
+  cf v[32];
+  if constexpr (STG) {
+    {
+      const int sl = tid % (2 * G);
+      int rk = 0;
+      bool ok = false;
+      {
+        const int jj = MIR ? (int)jb * G + (sl < G ? sl : sl - G) : (int)jb * G + (sl >> 1);
+        const bool isb = MIR ? sl >= G : (sl & 1) != 0;
+        int l, lbb;
+        bool bex = true;
+        if (MIR) {
+          l = c - jj;
+          lbb = (c + jj) & (P - 1);
+          bex = (jj != 0) && (lbb != l);
+        } else {
+          l = line_lo + 2 * jj;
+          lbb = l + 1;
+        }
+        const int line = isb ? lbb : l;
+        rk = (line - line_lo + P) & (P - 1);
+        ok = jj < p.n_jobs && rk < p.n_lines && (!isb || bex);
+      }
+      const unsigned lbase = ok ? (unsigned)rk * ls4 : kOOB;
+#pragma unroll 8
+      for (int u = tid / (2 * G); u < M; u += NT / (2 * G))
+        stg[u * SP + sl] = buf_ld(src, ok ? lbase + (unsigned)(u * ps4) : kOOB);
+    }
+    __syncthreads();
+    const int sa = MIR ? jl : 2 * jl, sb = MIR ? G + jl : 2 * jl + 1;
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+      const int m = n1 + Ma * jj;
+      const int ub1 = MIR ? (M - 1 - (m + 1024)) : m + 1024, ub0 = MIR ? (M - 1 - m) : m;
+      const cf z0 = {stg[(m + 1024) * SP + sa], stg[ub1 * SP + sb]};
+      const cf z1 = {stg[m * SP + sa], stg[ub0 * SP + sb]};
+      const cf r = rot(z1);
+      const cf w = buf_ld2(tsplit, tw_lane, Ma * jj * 8);
+      v[jj] = cmul({fmaf(sgn_h, z0.x, r.x), fmaf(sgn_h, z0.y, r.y)}, w);
+    }
+    __syncthreads();      // the tile is free: exchanges may overwrite it
+  } else {
+    constexpr int kLdPol = (KIND == kRowPass && MIR) ? kCpolNonTemporal : kCpolDefault;
+    const unsigned base_a = a_ok ? (unsigned)ra * ls4 : kOOB;
+    const unsigned base_b = b_ok ? (unsigned)rb * ls4 : kOOB;
+    // window input: b' at window position u is b at N - 1 - u; whole line: at P - 1 - u.
+    // Positions are n1 + pos with pos <= L - Ma: the lane part goes in the
+    // per-lane offset, the rest (never negative) in the uniform one.
+    constexpr int L = IO == kIoFullWin ? P : M;
+    const unsigned la_lane = base_a + (unsigned)(n1 * ps4);
+    const unsigned lb_lane = base_b + (unsigned)((MIR ? (Ma - 1 - n1) : n1) * ps4);
+    auto ldz = [&](int pos) -> cf {
+      const int ob = MIR ? (L - Ma - pos) : pos;
+      return {buf_ld<kLdPol>(src, la_lane, pos * ps4), buf_ld<kLdPol>(src, lb_lane, ob * ps4)};
+    };
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+      cf z0, z1;
+      if constexpr (IO == kIoFullWin) {
+        const cf y0 = ldz(Ma * jj), y1 = ldz(Ma * jj + 1024), y2 = ldz(Ma * jj + 2048), y3 = ldz(Ma * jj + 3072);
+        z0 = {fmaf(sgn_h, y2.x, y0.x), fmaf(sgn_h, y2.y, y0.y)};
+        z1 = {fmaf(sgn_h, y3.x, y1.x), fmaf(sgn_h, y3.y, y1.y)};
+        const cf r = rot(z1);
+        const cf w = buf_ld2(tsplit, tw_lane, Ma * jj * 8);
+        v[jj] = cmul({z0.x + r.x, z0.y + r.y}, w);
+      } else {
+        z0 = ldz(Ma * jj + 1024);
+        z1 = ldz(Ma * jj);
+        const cf r = rot(z1);
+        const cf w = buf_ld2(tsplit, tw_lane, Ma * jj * 8);
+        v[jj] = cmul({fmaf(sgn_h, z0.x, r.x), fmaf(sgn_h, z0.y, r.y)}, w);
+      }
+    }
+  }
+
+  auto wsync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  // ---- 32-point transforms over j: bins k2 = 2k + e; twiddle W_M^(n1 k2) ----
+  Dft<32, -1>::run(v);
+#pragma unroll
+  for (int k = 0; k < 32; ++k)
+    v[k] = cmul(v[k], buf_ld2(tfwd, (unsigned)(e * Ma + n1) * 8u, 2 * k * Ma * 8));
+
+  // ---- exchange 1 (this wave's area): lane L takes row k2 = L ----
+  cf w[32];
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (part) wsync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) xa[(2 * k + e) * ROWP + n1] = part ? v[k].y : v[k].x;
+    wsync();
+#pragma unroll
+    for (int c1 = 0; c1 < 32; ++c1) {
+      const float t = xa[lane * ROWP + c1];
+      if (part) w[c1].y = t;
+      else w[c1].x = t;
+    }
+  }
+
+  // ---- step C: 32-point transform over n1, phasor, inverse, twiddle W_M^(-n1 k2) ----
+  {
+    const int k2 = lane;
+    Dft<32, -1>::run(w);
+    const cf tlo = phase_exp((double)(2 * k2 + h), q, 1.0f);
+    const bool nyq_lane = (h == 0) && (k2 == 0);
+#pragma unroll
+    for (int k1 = 0; k1 < 32; ++k1) {
+      cf ph = cmul(tlo, ptab[k1]);
+      if (k1 == Ma / 2 && nyq_lane) ph.y = 0.f;   // real, symmetric Nyquist term
+      w[k1] = cmul(w[k1], ph);
+    }
+    Dft<32, +1>::run(w);
+#pragma unroll
+    for (int c1 = 0; c1 < 32; ++c1) w[c1] = cmul(w[c1], buf_ld2(tinv, (unsigned)k2 * 8u, c1 * Mb * 8));
+  }
+
+  // ---- exchange 2: lane (e, n1) takes k2 = 2k + e of column n1 ----
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    wsync();
+#pragma unroll
+    for (int c1 = 0; c1 < 32; ++c1) xa[lane * ROWP + c1] = part ? w[c1].y : w[c1].x;
+    wsync();
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      const float t = xa[(2 * k + e) * ROWP + n1];
+      if (part) v[k].y = t;
+      else v[k].x = t;
+    }
+  }
+
+  // ---- 32-point inverse transforms over k: Y_e[j]; scaled by conj(T[h][e][n1][j]) ----
+  Dft<32, +1>::run(v);
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) v[jj] = cmulc(v[jj], buf_ld2(tsplit, tw_lane, Ma * jj * 8));
+
+  // ---- combine the e halves: lane (e, n1) gets P = X0 + X1 and M = X0 - X1 at j = 2i + e ----
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const auto rx = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i].x), __float_as_uint(v[2 * i + 1].x),
+                                                     false, false);
+    const auto ry = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i].y), __float_as_uint(v[2 * i + 1].y),
+                                                     false, false);
+    const cf x0 = {__uint_as_float(rx[0]), __uint_as_float(ry[0])};
+    const cf x1 = {__uint_as_float(rx[1]), __uint_as_float(ry[1])};
+    v[2 * i] = cadd(x0, x1);         // P
+    v[2 * i + 1] = csub(x0, x1);     // M
+  }
+
+  // ---- combine the h waves through LDS: wave 0 sends M0 and keeps P0, wave 1
+  // sends P1 and keeps i M1; own = P0 or i M1, other = P1 or M0.  Each wave
+  // writes its own area (its earlier reads of it come first in program order)
+  // and reads the other's after the barrier. ----
+  {
+    float2* xa2 = reinterpret_cast<float2*>(xa);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const cf s = h ? v[2 * i] : v[2 * i + 1];
+      xa2[i * 64 + lane] = make_float2(s.x, s.y);
+    }
+  }
+  __syncthreads();
+  cf own[16], oth[16];
+  {
+    const float2* xo2 = reinterpret_cast<const float2*>(xo);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float2 t = xo2[i * 64 + lane];
+      oth[i] = {t.x, t.y};
+      own[i] = h ? cf{-v[2 * i + 1].y, v[2 * i + 1].x} : v[2 * i];
+    }
+  }
+  // outputs X = other + own at m + 1024 h and Y = +-(own - other) at m + 1024 h + 2048
+  // (wave 0: X = P0 + P1 at q = 0, Y = P0 - P1 at q = 2; wave 1: X = M0 + i M1 at
+  // q = 1, Y = M0 - i M1 at q = 3), m = n1 + 32 j, j = 2i + e
+  const float ysg = h ? -1.0f : 1.0f;
+  if constexpr (STG) {
+    __syncthreads();                 // the exchange areas (aliasing the tile) are read
+    const int sa = MIR ? jl : 2 * jl, sb = MIR ? G + jl : 2 * jl + 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int m = n1 + Ma * (2 * i + e);
+      // window positions: q = 1 (wave 1, X) at m, q = 2 (wave 0, Y) at m + 1024
+      const cf y = h ? cadd(oth[i], own[i]) : csub(own[i], oth[i]);
+      const int u = h ? m : m + 1024;
+      stg[u * SP + sa] = y.x;
+      stg[(MIR ? M - 1 - u : u) * SP + sb] = y.y;
+    }
+    __syncthreads();
+    {
+      const int sl = tid % (2 * G);
+      int rk = 0;
+      bool ok = false;
+      {
+        const int jj = MIR ? (int)jb * G + (sl < G ? sl : sl - G) : (int)jb * G + (sl >> 1);
+        const bool isb = MIR ? sl >= G : (sl & 1) != 0;
+        int l, lbb;
+        bool bex = true;
+        if (MIR) {
+          l = c - jj;
+          lbb = (c + jj) & (P - 1);
+          bex = (jj != 0) && (lbb != l);
+        } else {
+          l = line_lo + 2 * jj;
+          lbb = l + 1;
+        }
+        const int line = isb ? lbb : l;
+        const int rkk = (line - line_lo + P) & (P - 1);
+        ok = jj < p.n_jobs && rkk < p.n_lines && (!isb || bex);
+        rk = (line - p.dst_line_lo + P) & (P - 1);
+      }
+      const unsigned dls4 = (unsigned)p.dst_ls * 4u;
+      const int dps4 = p.dst_ps * 4;
+      const unsigned lbase = ok ? (unsigned)rk * dls4 : kOOB;
+#pragma unroll 8
+      for (int u = tid / (2 * G); u < M; u += NT / (2 * G))
+        buf_st(dst, ok ? lbase + (unsigned)(u * dps4) : kOOB, stg[u * SP + sl]);
+    }
+    return;
+  } else {
+    const int dst_lo = p.dst_line_lo;
+    const unsigned dls4 = (unsigned)p.dst_ls * 4u;
+    const int dps4 = p.dst_ps * 4;
+    const int orow_a = (la - dst_lo + P) & (P - 1), orow_b = (lb2 - dst_lo + P) & (P - 1);
+    const unsigned obase_a = a_ok ? (unsigned)orow_a * dls4 : kOOB;
+    const unsigned obase_b = b_ok ? (unsigned)orow_b * dls4 : kOOB;
+    // Output positions u = ul + uc: ul = n1 + Ma e per lane, uc = 2 i Ma +
+    // 1024 h (+ 2048) uniform, at most UC.  b' is reversed about the end of the
+    // output line (length LO): b at LO - 1 - u = (LO - 1 - ul - UC) + (UC - uc).
+    constexpr int LO = IO == kIoWinFull ? P : M;
+    constexpr int UC = IO == kIoWinFull ? 30 * Ma + 1024 + 2048 : 30 * Ma + 1024;
+    const int ul = n1 + Ma * e;
+    const unsigned oa_lane = obase_a + (unsigned)(ul * dps4);
+    const unsigned ob_lane = obase_b + (unsigned)((MIR ? LO - 1 - UC - ul : ul) * dps4);
+    auto st2 = [&](cf y, int uc) {
+      buf_st(dst, oa_lane, y.x, uc * dps4);
+      buf_st(dst, ob_lane, y.y, (MIR ? UC - uc : uc) * dps4);
+    };
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const cf X = cadd(oth[i], own[i]);
+      const cf Y = {ysg * (own[i].x - oth[i].x), ysg * (own[i].y - oth[i].y)};
+      if constexpr (IO == kIoWinFull) {
+        st2(X, 2 * i * Ma + 1024 * h);
+        st2(Y, 2 * i * Ma + 1024 * h + 2048);
+      } else {
+        // window: wave 1 stores X at window position m, wave 0 stores Y at m + 1024
+        st2(h ? X : Y, 2 * i * Ma + 1024 * (1 - h));
+      }
+    }
+  }
+}
+
+template <int KIND, int G, int IO, bool MIR>
+__global__ void __launch_bounds__(G * 128) __attribute__((amdgpu_waves_per_eu(4, 4)))
+line_pass_split_kernel(const LinePass p) {
+  const unsigned nb = gridDim.x;
+  const unsigned b = blockIdx.x;
+  const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const unsigned bpf = (unsigned)p.blocks_per_frame;
+  const unsigned f = lb / bpf;
+  const unsigned jb = lb - f * bpf;
+  if (p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
+    return;   // whole block leaves together, before any barrier
+  process_block_split<KIND, G, IO, MIR, KIND == kColPass>(p, f, jb);
+}
+
 template <int KIND, int IO>
 constexpr bool staged() {
   return GRAPHIC_COL_STAGED && KIND == kColPass && IO == kIoWinWin && lanes_on_jobs<KIND>();
@@ -848,9 +1254,64 @@ static hipError_t launch_tile_major(const LinePass& p, int kind, int variant, hi
   return hipErrorInvalidValue;
 }
 
+// Two-wave jobs at M = 2048: G jobs per block (row passes 1; staged column
+// passes 4, two blocks per compute unit, or 2 as the tuned alternative).
+// Half-turned frames take the general one-wave path.
+#ifndef GRAPHIC_SPLIT_COL_G
+#define GRAPHIC_SPLIT_COL_G 4
+#endif
+template <int KIND, int G, int IO, bool MIR>
+static hipError_t launch_split(LinePass p, hipStream_t st) {
+  constexpr bool STG = KIND == kColPass;
+  constexpr size_t lds = (size_t)split_lds_floats<KIND, G, STG>() * sizeof(float);
+  static_assert(lds <= 160 * 1024, "LDS per block above 160 KiB");
+  p.blocks_per_frame = (p.n_jobs + G - 1) / G;
+  const long long blocks = p.n_frames * (long long)p.blocks_per_frame;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipError_t e = set_dynamic_lds(line_pass_split_kernel<KIND, G, IO, MIR>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((line_pass_split_kernel<KIND, G, IO, MIR>), dim3((unsigned)blocks), dim3(G * 128), lds, st, p);
+  e = hipGetLastError();
+  const bool flipped = p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse);
+  if (e != hipSuccess || !flipped) return e;
+  // half-turned frames: general path over the device-side list (one-wave jobs)
+  constexpr int GF = KIND == kColPass ? col_jobs_per_block<kSplitM>() : row_jobs_per_block<kSplitM>();
+  p.blocks_per_frame = (p.n_jobs + GF - 1) / GF;
+  const long long fblocks = p.n_frames * (long long)p.blocks_per_frame;
+  const size_t lds_flip = (size_t)lds_floats<kSplitM, KIND, GF, false>() * sizeof(float);
+  if ((e = set_dynamic_lds(line_pass_flipped_kernel<kSplitM, KIND, GF, MIR, 0>, lds_flip)) != hipSuccess) return e;
+  const long long fb = std::min<long long>(fblocks, 2048);
+  hipLaunchKernelGGL((line_pass_flipped_kernel<kSplitM, KIND, GF, MIR, 0>), dim3((unsigned)fb),
+                     dim3(GF * Shape<kSplitM>::JOB), lds_flip, st, p);
+  return hipGetLastError();
+}
+
+static hipError_t launch_split_m(const LinePass& p, int kind, int variant, hipStream_t st, bool* done) {
+  *done = true;
+  const int io = io_kind(p);
+  if (kind == kRowPass) {
+    if (io == kIoWinWin) return p.mirror ? launch_split<kRowPass, 1, kIoWinWin, true>(p, st)
+                                         : launch_split<kRowPass, 1, kIoWinWin, false>(p, st);
+    if (io == kIoWinFull && p.mirror) return launch_split<kRowPass, 1, kIoWinFull, true>(p, st);
+    if (io == kIoFullWin && p.mirror) return launch_split<kRowPass, 1, kIoFullWin, true>(p, st);
+  } else if (io == kIoWinWin) {
+    if (variant == 1) return p.mirror ? launch_split<kColPass, 2, kIoWinWin, true>(p, st)
+                                      : launch_split<kColPass, 2, kIoWinWin, false>(p, st);
+    return p.mirror ? launch_split<kColPass, GRAPHIC_SPLIT_COL_G, kIoWinWin, true>(p, st)
+                    : launch_split<kColPass, GRAPHIC_SPLIT_COL_G, kIoWinWin, false>(p, st);
+  }
+  *done = false;
+  return hipSuccess;
+}
+
 template <int M>
 static hipError_t launch_m(const LinePass& p, int kind, int variant, hipStream_t st) {
   if (p.src_tm || p.dst_tm) return launch_tile_major<M>(p, kind, variant, st);
+  if constexpr (M == kSplitM) {
+    bool done = false;
+    const hipError_t e = launch_split_m(p, kind, variant, st, &done);
+    if (done) return e;
+  }
   if (kind == kRowPass) return launch_io<M, kRowPass, row_jobs_per_block<M>()>(p, st);
   constexpr int GA = col_jobs_alt<M>();
   if constexpr (GA > 0 && GRAPHIC_COL_STAGED && lanes_on_jobs<kColPass>()) {

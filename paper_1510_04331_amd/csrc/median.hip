@@ -612,7 +612,125 @@ __global__ void __launch_bounds__(64) select_frames_kernel(const double* __restr
   if (g == 0) counts[f] = c;
 }
 
+// ---------------------------------------------------------------------------
+// Stacks too deep for registers (T > 4096, e.g. a whole night of frames): the
+// same exact median, by a radix select that streams the stack from HBM once
+// per 8-bit digit instead of reading it once into registers.  A block owns 64
+// consecutive pixels (one 256-byte segment of every frame) and keeps one
+// 256-bin histogram per pixel in LDS; its four waves take frames w, w + 4,
+// w + 8, ... of all 64 pixels.  After the four digits lo, the key of rank
+// (T-1)/2, is known exactly, with its rank among the keys equal to it and how
+// many there are; when rank T/2 falls past that run (even T), one more pass
+// takes the smallest key above lo.  With resid, a last pass writes value -
+// median for every frame (in place allowed: each thread rewrites the values
+// it reads).
+// ---------------------------------------------------------------------------
+constexpr int kStreamPix = 64;
+constexpr int kStreamWaves = 4;
+constexpr int kStreamPitch = 257;       // words per pixel histogram (odd: spreads the banks)
+constexpr int kStreamUnroll = 8;        // frames per thread in flight
+
+__global__ void __launch_bounds__(kStreamPix * kStreamWaves)
+median_stream_kernel(const float* __restrict__ stack, long long T, long long npix, float* __restrict__ out,
+                     float* resid) {
+  extern __shared__ unsigned shist[];                  // kStreamPix x kStreamPitch words
+  __shared__ unsigned s_prefix[kStreamPix], s_rank[kStreamPix], s_cnt[kStreamPix], s_min[kStreamPix];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long pix = (long long)blockIdx.x * kStreamPix + lane;
+  const bool ok = pix < npix;
+  const float* col = stack + (ok ? pix : 0);
+  if (tid < kStreamPix) {
+    s_prefix[tid] = 0u;
+    s_rank[tid] = (unsigned)((T - 1) / 2);
+    s_min[tid] = 0xFFFFFFFFu;
+  }
+  unsigned mask = 0u;
+  for (int d = 3; d >= 0; --d) {
+    for (int i = tid; i < kStreamPix * kStreamPitch; i += kStreamPix * kStreamWaves) shist[i] = 0u;
+    __syncthreads();
+    const unsigned prefix = s_prefix[lane];
+    const int shft = 8 * d;
+    unsigned* h = shist + lane * kStreamPitch;
+    if (ok) {
+      long long t = wave;
+      for (; t + (kStreamUnroll - 1) * kStreamWaves < T; t += kStreamUnroll * kStreamWaves) {
+        unsigned k[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) k[u] = key_of(col[(t + u * kStreamWaves) * npix]);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+          if ((k[u] & mask) == prefix) atomicAdd(&h[(k[u] >> shft) & 0xFFu], 1u);
+      }
+      for (; t < T; t += kStreamWaves) {
+        const unsigned k = key_of(col[t * npix]);
+        if ((k & mask) == prefix) atomicAdd(&h[(k >> shft) & 0xFFu], 1u);
+      }
+    }
+    __syncthreads();
+    // wave w scans the histograms of pixels w, w + 4, ...: lane l sums bins
+    // 4l .. 4l + 3, a wave prefix sum finds the lane whose bins hold rank r
+    for (int q = wave; q < kStreamPix; q += kStreamWaves) {
+      const unsigned r = s_rank[q];
+      const unsigned* hq = shist + q * kStreamPitch + 4 * lane;
+      const unsigned c0 = hq[0], c1 = hq[1], c2 = hq[2], c3 = hq[3];
+      const unsigned x = c0 + c1 + c2 + c3;
+      const unsigned incl = wave_incl_scan(x);
+      const unsigned long long hit = __ballot(incl > r);
+      const int l0 = hit ? __ffsll((long long)hit) - 1 : 63;
+      if (lane == l0) {
+        unsigned acc = incl - x;                       // keys below this lane's bins
+        int b = 0;
+        unsigned c = c0;
+        if (acc + c0 <= r) { acc += c0; b = 1; c = c1;
+          if (acc + c1 <= r) { acc += c1; b = 2; c = c2;
+            if (acc + c2 <= r) { acc += c2; b = 3; c = c3; } } }
+        s_prefix[q] |= (unsigned)(4 * lane + b) << shft;
+        s_rank[q] = r - acc;
+        s_cnt[q] = c;
+      }
+    }
+    mask |= 0xFFu << shft;
+    __syncthreads();
+  }
+  // s_prefix is lo's key, s_rank its rank among the keys equal to it and
+  // s_cnt how many keys equal it: rank T/2 is lo itself iff it stays in that run
+  const unsigned lo_key = s_prefix[lane];
+  const unsigned stepr = (unsigned)(T / 2 - (T - 1) / 2);        // 0 (odd T) or 1
+  const bool need_hi = ok && s_rank[lane] + stepr >= s_cnt[lane];
+  if (__syncthreads_or(need_hi)) {                               // block-uniform
+    if (need_hi) {
+      unsigned m = 0xFFFFFFFFu;
+      for (long long t = wave; t < T; t += kStreamWaves) {
+        const unsigned k = key_of(col[t * npix]);
+        if (k > lo_key) m = min(m, k);
+      }
+      atomicMin(&s_min[lane], m);
+    }
+    __syncthreads();
+  }
+  const float lo = val_of(lo_key);
+  const float hi = need_hi ? val_of(s_min[lane]) : lo;
+  const float med = (lo + hi) * 0.5f;
+  if (wave == 0 && ok) out[pix] = med;
+  if (resid != nullptr && ok) {
+    float* rc = resid + pix;
+    for (long long t = wave; t < T; t += kStreamWaves) rc[t * npix] = col[t * npix] - med;
+  }
+}
+
 }  // namespace
+
+// Deep stacks: one launch of the streaming select.
+static hipError_t launch_median_stream(const float* stack, long long T, long long npix, float* out, float* resid,
+                                       hipStream_t s) {
+  const size_t lds = (size_t)kStreamPix * kStreamPitch * sizeof(unsigned);
+  const long long blocks = (npix + kStreamPix - 1) / kStreamPix;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (hipError_t e = set_dynamic_lds(median_stream_kernel, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL(median_stream_kernel, dim3((unsigned)blocks), dim3(kStreamPix * kStreamWaves), lds, s, stack, T,
+                     npix, out, resid);
+  return hipGetLastError();
+}
 
 template <int PIX>
 static hipError_t launch_median_pix(const float* stack, long long T, long long npix, float* out, float* resid,
@@ -745,6 +863,7 @@ hipError_t launch_median_tile_major(const float* stack, long long T, long long n
 hipError_t launch_median(const float* stack, long long T, long long npix, float* out, float* resid, int variant,
                          hipStream_t s) {
   if (T <= 0 || npix <= 0) return hipSuccess;
+  if (T > (long long)kGroups * 64) return launch_median_stream(stack, T, npix, out, resid, s);
   return variant == 1 ? launch_median_pix<8>(stack, T, npix, out, resid, s)
                       : launch_median_pix<16>(stack, T, npix, out, resid, s);
 }

@@ -58,7 +58,9 @@ def test_workspace_sizes(lib):
     assert sz.value >= 16 * 128 * 256 * 4
     assert lib.graphic_workspace_size(None, _abi.OP_ADI, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
     assert sz.value >= 16 * 128 * 128 * 4 + 16 * 128 * 256 * 4
-    g_big = _abi.Geom(5000, 64, 0, 0)
+    deep = _abi.Geom(100_000, 64, 0, 0)        # a night of frames: the streaming select
+    assert lib.graphic_workspace_size(None, _abi.OP_MEDIAN, ctypes.byref(deep), ctypes.byref(sz)) == _abi.OK
+    g_big = _abi.Geom((1 << 24) + 1, 64, 0, 0)
     assert lib.graphic_workspace_size(None, _abi.OP_MEDIAN, ctypes.byref(g_big), ctypes.byref(sz)) == \
         _abi.ERR_UNSUPPORTED
     bad = _abi.Geom(16, 7, 0, 0)
