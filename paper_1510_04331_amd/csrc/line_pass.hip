@@ -1064,8 +1064,17 @@ __device__ __forceinline__ void process_block_split(const LinePass& p, const uns
   }
 }
 
+// Occupancy of the two-wave jobs (waves per SIMD), measured on MI355X at
+// 256 x 2048^2: 4, except the first x-shear (window in, whole line out),
+// which is fastest at 3 (5.1 against 6.5 ms).
+template <int IO>
+constexpr int split_waves_per_eu() {
+  return IO == kIoWinFull ? 3 : 4;
+}
+
 template <int KIND, int G, int IO, bool MIR>
-__global__ void __launch_bounds__(G * 128) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(G * 128)
+__attribute__((amdgpu_waves_per_eu(split_waves_per_eu<IO>(), split_waves_per_eu<IO>())))
 line_pass_split_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
@@ -1254,12 +1263,12 @@ static hipError_t launch_tile_major(const LinePass& p, int kind, int variant, hi
   return hipErrorInvalidValue;
 }
 
-// Two-wave jobs at M = 2048: G jobs per block (row passes 1; staged column
-// passes 4, two blocks per compute unit, or 2 as the tuned alternative).
+// Two-wave jobs at M = 2048: G jobs per block.  Row passes: 1.  Staged
+// column passes: 4 for the shift's pairing of adjacent columns (two blocks
+// per compute unit), 8 for the mirrored pairs of the y-shear (one block, but
+// row runs of 32 bytes on each side instead of 16: 10.5 against 12.3 ms at
+// 256 x 2048^2); the other width is the tuned alternative.
 // Half-turned frames take the general one-wave path.
-#ifndef GRAPHIC_SPLIT_COL_G
-#define GRAPHIC_SPLIT_COL_G 4
-#endif
 template <int KIND, int G, int IO, bool MIR>
 static hipError_t launch_split(LinePass p, hipStream_t st) {
   constexpr bool STG = KIND == kColPass;
@@ -1295,10 +1304,10 @@ static hipError_t launch_split_m(const LinePass& p, int kind, int variant, hipSt
     if (io == kIoWinFull && p.mirror) return launch_split<kRowPass, 1, kIoWinFull, true>(p, st);
     if (io == kIoFullWin && p.mirror) return launch_split<kRowPass, 1, kIoFullWin, true>(p, st);
   } else if (io == kIoWinWin) {
-    if (variant == 1) return p.mirror ? launch_split<kColPass, 2, kIoWinWin, true>(p, st)
-                                      : launch_split<kColPass, 2, kIoWinWin, false>(p, st);
-    return p.mirror ? launch_split<kColPass, GRAPHIC_SPLIT_COL_G, kIoWinWin, true>(p, st)
-                    : launch_split<kColPass, GRAPHIC_SPLIT_COL_G, kIoWinWin, false>(p, st);
+    if (p.mirror) return variant == 1 ? launch_split<kColPass, 4, kIoWinWin, true>(p, st)
+                                      : launch_split<kColPass, 8, kIoWinWin, true>(p, st);
+    return variant == 1 ? launch_split<kColPass, 8, kIoWinWin, false>(p, st)
+                        : launch_split<kColPass, 4, kIoWinWin, false>(p, st);
   }
   *done = false;
   return hipSuccess;

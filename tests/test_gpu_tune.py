@@ -24,7 +24,7 @@ def _reduce(G, cube, p):
     return [t.cpu().numpy().tobytes() for t in (fin, psf, res)]
 
 
-@pytest.mark.parametrize("T,N", [(70, 256), (33, 512)])
+@pytest.mark.parametrize("T,N", [(70, 256), (33, 512), (12, 2048)])
 def test_variants_bit_identical(torch_dev, T, N):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
