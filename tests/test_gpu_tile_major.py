@@ -1,6 +1,7 @@
 """Tile-major workspace stacks of the ADI reduction (frames of 1024 x 1024
-pixels, P = 2N; other sizes keep the frame-major stack, which the 2048 case
-checks through the same comparison).
+pixels, P = 2N; other sizes keep the frame-major stack, which the 2048 cases
+check through the same comparison: the workspace stack against the caller's
+residual array, with small rotation chunks).
 
 When the caller asks for no residuals and the cube is not overwritten, the
 reduction keeps its stack in the workspace in the tile-major layout (the
@@ -54,7 +55,7 @@ def _small_ws(torch, dev, bytes_default, N, F, chunk):
 @pytest.mark.parametrize("N,T,wide,chunk", [(1024, 37, True, None), (1024, 70, False, 6), (1024, 1, True, None),
                                              (1024, 64, True, 5), (1024, 32, True, None), (1024, 130, True, None),
                                              (1024, 2500, False, None),
-                                             (2048, 19, True, 4)])
+                                             (2048, 19, True, 4), (2048, 70, False, None), (2048, 33, True, 7)])
 def test_tile_major_equals_frame_major(torch_dev, N, T, wide, chunk):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
@@ -99,6 +100,24 @@ def test_tile_major_against_oracle(torch_dev):
     fin, psf = G.adi_reduce(cube, q.dx, q.dy, q.parang, psf=True)
     host = cube.cpu().numpy()
     workers = max(1, min(12, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        ref = O.adi_reduce(host, q.dx, q.dy, q.parang, map_fn=lambda f, a: pool.map(f, a, chunksize=1))
+    scale = np.linalg.norm(ref["psf"])
+    assert np.linalg.norm(psf.cpu().numpy() - ref["psf"]) / scale <= REL_L2
+    assert np.linalg.norm(fin.cpu().numpy() - ref["final"]) / scale <= REL_L2
+
+
+def test_workspace_stack_2048_against_oracle(torch_dev):
+    """The 2048^2 reduction with its stack in the workspace (two-wave line
+    passes, no residuals requested) against the oracle."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("workspace-stack ADI 5 x 2048^2 against the oracle", flush=True)
+    q = _params(2048, 5, 5, True)
+    cube = synth.render_device(q, dev)
+    fin, psf = G.adi_reduce(cube, q.dx, q.dy, q.parang, psf=True)
+    host = cube.cpu().numpy()
+    workers = max(1, min(5, os.cpu_count() or 1))
     with mp.get_context("spawn").Pool(workers) as pool:
         ref = O.adi_reduce(host, q.dx, q.dy, q.parang, map_fn=lambda f, a: pool.map(f, a, chunksize=1))
     scale = np.linalg.norm(ref["psf"])
