@@ -23,6 +23,9 @@ Two more workloads print their own JSON line:
     python bench.py --workload preprocess  pre-processing of Sect. 3.2 of
         1024 frames of 512^2: star-masked master skies of 8 groups of 128
         frames, nearest-sky subtraction, bad-pixel map and repair
+    python bench.py --workload mfma     one 32-point DFT stage of the line
+        passes as a DFT-as-GEMM on the matrix cores (v_mfma_f32_32x32x2f32)
+        against the register codelet, both checked against a direct DFT
     python bench.py --workload quality  the image-quality test of Sect. 4.1:
         256 frames of 1024^2 shifted by (3.5, 2.7) px and back and rotated by
         11.3 deg and back, residual RMS in 2-px annuli; the third-order
@@ -241,6 +244,59 @@ def bench_batch(args):
     print("graph done", file=sys.stderr, flush=True)
     mb, mp, mg = min(tb), min(tp), min(tg)
 
+    # many small cubes (64 cubes of 16 frames of 128^2): one batched call
+    # against one call per cube, where launches rather than bytes set the time
+    sq = [synth.make_params(1, seed=synth.BASE_SEED + 400 + k) for k in range(64)]
+    scubes = [torch.from_numpy(synth.render_host(q)).to(dev) for q in sq]
+    sargs = ([torch.tensor(q.dx, dtype=torch.float64, device=dev) for q in sq],
+             [torch.tensor(q.dy, dtype=torch.float64, device=dev) for q in sq],
+             [torch.tensor(q.parang, dtype=torch.float64, device=dev) for q in sq])
+    sws = torch.empty(G.batch_workspace_size(scubes), dtype=torch.uint8, device=dev)
+
+    def small_batched():
+        G.adi_reduce_batch(scubes, *sargs, workspace=sws)
+
+    def small_per_cube():
+        for k in range(len(scubes)):
+            G.adi_reduce_batch([scubes[k]], [sargs[0][k]], [sargs[1][k]], [sargs[2][k]], workspace=sws)
+
+    def best_ms(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return 1e3 * min(ts)
+    small_frames = sum(q.T for q in sq)
+    sb_ms, sp_ms = best_ms(small_batched), best_ms(small_per_cube)
+
+    # the plain per-frame path on a sample of the batch (the first cube of
+    # each size): every frame shifted and rotated by its own calls
+    def per_frame_rate():
+        frames, t_all = 0, 0.0
+        for N in sorted(set(p.N for p in ps)):
+            k = next(i for i, p in enumerate(ps) if p.N == N)
+            c = cubes[k]
+            fills[k](c)
+            n = min(c.shape[0], 32)
+            one_dx = [dx[k][i:i + 1] for i in range(n)]
+            one_dy = [dy[k][i:i + 1] for i in range(n)]
+            one_pa = [pa[k][i:i + 1] for i in range(n)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                f = G.shift(c[i:i + 1], one_dx[i], one_dy[i])
+                G.rotate(f, -one_pa[i], out=f)
+            torch.cuda.synchronize()
+            t_all += time.perf_counter() - t0
+            frames += n
+        return frames / t_all
+
+    pf_rate = per_frame_rate()
+
     # small cube (16 frames of 128^2): host-side cost of one eager call vs one
     # graph replay, back to back on one stream
     q = synth.make_params(1)
@@ -271,6 +327,12 @@ def bench_batch(args):
            "per_cube_path": {"value": round(frames / mp, 1), "ms_per_step": round(1e3 * mp, 3)},
            "graph_replay": {"value": round(frames / mg, 1), "ms_per_step": round(1e3 * mg, 3)},
            "tuning": tuning.strip().split("\n"),
+           "small_cubes_64x16x128": {"batched_frames_per_s": round(small_frames / (sb_ms * 1e-3), 1),
+                                     "per_cube_frames_per_s": round(small_frames / (sp_ms * 1e-3), 1),
+                                     "batched_ms": round(sb_ms, 3), "per_cube_ms": round(sp_ms, 3)},
+           "per_frame_path": {"frames_shifted_rotated_per_s": round(pf_rate, 1),
+                              "sample": "first cube of each size, up to 32 frames each, one shift and one rotation "
+                                        "call per frame"},
            "small_cube_16x128_us_per_reduction": {"eager": round(eager_us, 1), "graph": round(graph_us, 1)},
            "step_ms_all": [round(1e3 * t, 3) for t in tb]}
     print(json.dumps(out), flush=True)
@@ -470,6 +532,25 @@ def bench_quality(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mfma(args):
+    """Runs the measurement program built next to the library (one DFT stage
+    on the matrix cores against the register codelet) and prints its result
+    as one JSON line."""
+    import subprocess
+    exe = os.path.join(HERE, "paper_1510_04331_amd", "dft32_mfma")
+    if not os.path.exists(exe):
+        raise RuntimeError("dft32_mfma is not built; run __graft_entry__.build()")
+    r = subprocess.run([exe, str(1 << 20), "64"], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("dft32_mfma failed (%d): %s %s" % (r.returncode, r.stdout, r.stderr))
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    out = {"metric": "time per 32-point complex DFT stage and vector, matrix cores vs register codelet",
+           "value": res["mfma_over_valu_time"], "unit": "ratio (mfma / valu time)", "n_gpus": 1, "steps": 5,
+           "warmup": 1, "ms_per_step": res["mfma_32x32x2_f32"]["ms"], "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": res["what"]}, "result": res}
+    print(json.dumps(out), flush=True)
+
+
 def bench_served(args):
     import numpy as np
     import torch
@@ -588,7 +669,8 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register", "preprocess", "quality"),
+    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register", "preprocess", "quality",
+                                           "mfma"),
                     default="adi")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning (default launch shapes; keeps tuning launches out of profiles)")
@@ -622,6 +704,8 @@ def main():
         return bench_quality(args)
     if args.workload == "preprocess":
         return bench_preprocess(args)
+    if args.workload == "mfma":
+        return bench_mfma(args)
 
     cpu = None
     if not args.no_cpu_baseline:

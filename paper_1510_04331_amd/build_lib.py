@@ -47,12 +47,33 @@ def _compile(src, verbose, defines=()):
     return obj
 
 
+# Measurement programs (not part of the library): built next to it.
+EXPERIMENTS = {"dft32_mfma": "experiments/dft32_mfma.hip"}
+
+
+def _build_experiment(name, verbose):
+    exe = os.path.join(HERE, name)
+    cmd = [_hipcc()] + [f for f in COMMON if f != "-fPIC"] + DEVICE[2:] + \
+        [os.path.join(CSRC, EXPERIMENTS[name]), "-o", exe + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (name, r.stdout, r.stderr))
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 def build(verbose=False, jobs=4, out=None, defines=()):
     """Compile every source and link libgraphic.so next to this file (or to
-    ``out``), with optional extra ``-D`` definitions."""
+    ``out``), with optional extra ``-D`` definitions; also build the
+    measurement programs."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
+        exps = [ex.submit(_build_experiment, n, verbose) for n in EXPERIMENTS] if out is None else []
         objs = list(ex.map(lambda s: _compile(s, verbose, defines), SOURCES))
+        for f in exps:
+            f.result()
     lib = out or LIB
     tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
