@@ -57,6 +57,8 @@ def sources_sha256():
     import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(HERE, "paper_1510_04331_amd", "csrc", "*"))):
+        if not os.path.isfile(f):
+            continue
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
