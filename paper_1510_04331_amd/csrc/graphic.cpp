@@ -111,10 +111,13 @@ void host_tables(int M, std::vector<float2>& fwd, std::vector<float2>& inv, std:
       fwd[k2 * Ma + n1] = float2{(float)std::cos(a), (float)-std::sin(a)};
       inv[n1 * Mb + k2] = float2{(float)std::cos(a), (float)std::sin(a)};
     }
+  // fold factors of the odd half, stored as their offset from one:
+  // exp(-2 pi i m / 2M) - 1 = (-2 sin^2(a/2), -sin a); the even half (factor
+  // one, offset zero) is never read
   for (int m = 0; m < M; ++m) {
-    fold[m] = float2{1.0f, 0.0f};
     const double a = two_pi * (double)m / (2.0 * M);
-    fold[M + m] = float2{(float)std::cos(a), (float)-std::sin(a)};
+    const double sh = std::sin(0.5 * a);
+    fold[M + m] = float2{(float)(-2.0 * sh * sh), (float)-std::sin(a)};
   }
 }
 

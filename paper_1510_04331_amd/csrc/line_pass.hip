@@ -38,6 +38,8 @@
 
 #include <algorithm>
 
+#include <atomic>
+
 #include "dft_codelets.h"
 #include "internal.h"
 
@@ -131,6 +133,13 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 #ifndef GRAPHIC_ROW_W_1024
 #define GRAPHIC_ROW_W_1024 3
 #endif
+// Row passes at M = 1024 that read their twiddle factors from LDS
+// (persistent blocks of 16 waves) instead of the global tables, by index
+// pattern: bit 0 window to window, bit 1 window to full line (the first
+// x-shear, the measured gain), bit 2 full line to window.
+#ifndef GRAPHIC_ROW_LDS_TW
+#define GRAPHIC_ROW_LDS_TW 2
+#endif
 #ifndef GRAPHIC_COL_WAVE_LAYOUT
 #define GRAPHIC_COL_WAVE_LAYOUT 0
 #endif
@@ -199,6 +208,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, un
 
 constexpr unsigned kOOB = 0x80000000u;   // beyond every frame: reads 0, writes dropped
 
+// Products with a factor stored as its offset from one, w = 1 + d (the fold
+// table): x w = x + x d in four fused multiply-adds, the same count as a
+// plain complex product.  With d = 0 (the even half, whose lanes read the
+// table out of bounds and get zero) the result is x exactly.
+__device__ __forceinline__ cf cmul_1p(cf x, cf d) {
+  return {fmaf(x.x, d.x, fmaf(-x.y, d.y, x.x)), fmaf(x.x, d.y, fmaf(x.y, d.x, x.y))};
+}
+// x conj(1 + d)
+__device__ __forceinline__ cf cmulc_1p(cf x, cf d) {
+  return {fmaf(x.x, d.x, fmaf(x.y, d.y, x.x)), fmaf(x.y, d.x, fmaf(-x.x, d.y, x.y))};
+}
+
 // LDS floats of a block: exchange buffers (or, for staged column blocks, the
 // larger of those and the staging tile of M rows x 2G lines), then the
 // per-job phasor tables.
@@ -224,10 +245,14 @@ constexpr int lds_floats() {
 // row of the frame is then M / 16 chunks of 16 pixels, cs = 64 T bytes apart,
 // and each of the job's two rows gets its own wave-uniform descriptor (row
 // passes with M >= 1024 run one job per wave).
-template <int M, int KIND, int G, int IO, bool MIR, bool STG = false, int TM = 0>
-__device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb) {
+template <int M, int KIND, int G, int IO, bool MIR, bool STG = false, int TM = 0, bool TWL = false>
+__device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb,
+                                              float* wlds = nullptr, const float2* lfold = nullptr,
+                                              const float2* lfwd = nullptr) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
+  static_assert(!TWL || (KIND == kRowPass && G == 1 && JOB == 64 && Ma == Mb && !STG),
+                "LDS twiddles: one-wave row jobs of a square four-step split");
   static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
   constexpr bool TMS = (TM & 1) != 0, TMD = (TM & 2) != 0;
   static_assert(!TM || (M >= 1024 && (KIND == kColPass || G * JOB == 64)), "tile-major rows: one job per wave");
@@ -242,11 +267,13 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   constexpr int BUF = G * 2 * S::HALF;
   constexpr int SP = 2 * G + 1;                        // staging tile pitch (floats per row)
   extern __shared__ float lds_raw[];
-  float* lds = lds_raw;
+  // TWL: twiddles in LDS, and the wave's own exchange area and phasor table
+  // (wlds)
+  float* lds = TWL ? wlds : lds_raw;
   float* stg = lds_raw;                                // staging tile (aliases the exchange buffers)
-  cf* ptab = reinterpret_cast<cf*>(lds_raw + (lds_floats<M, KIND, G, STG>() - 2 * G * Ma));
+  cf* ptab = reinterpret_cast<cf*>(lds + (lds_floats<M, KIND, G, STG>() - 2 * G * Ma));
 
-  const int tid = threadIdx.x;
+  const int tid = TWL ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
   int jl, r;
   if constexpr (!LJ) {
     jl = tid / JOB;
@@ -379,6 +406,37 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // ---- load, pack and fold into this half's branch ----
   const float sg = h ? -1.0f : 1.0f;
   const unsigned tw_lane = (unsigned)(h * M + n1) * 8u;
+  // twiddle factors of this lane: fold / unfold offsets d = w - 1 (n = n1 +
+  // Ma n2 of half h; the even half reads out of bounds, d = 0, and fetches
+  // nothing), forward four-step (n1 k2), inverse four-step (the conjugate of
+  // the forward factor at (c1, n1) when Ma == Mb, so both read one table);
+  // from LDS when TWL
+  const unsigned tw_fold_lane = h ? tw_lane : kOOB;
+  auto tw_fold = [&](int n2) -> cf {
+    if constexpr (TWL) {
+      const float2 t = lfold[h * M + n1 + Ma * n2];
+      return {t.x, t.y};
+    }
+    else return buf_ld2(tfold, tw_fold_lane, Ma * n2 * 8);
+  };
+  auto tw_fwd = [&](int k2) -> cf {
+    if constexpr (TWL) {
+      const float2 t = lfwd[n1 + Ma * k2];
+      return {t.x, t.y};
+    }
+    else return buf_ld2(tfwd, (unsigned)n1 * 8u, k2 * Ma * 8);
+  };
+  auto tw_inv = [&](int c1, int qq) -> cf {
+    if constexpr (TWL) {
+      const float2 t = lfwd[n1 + Ma * c1];
+      return {t.x, -t.y};
+    } else if constexpr (Ma == Mb) {
+      const cf t = buf_ld2(tfwd, (unsigned)n1 * 8u, c1 * Ma * 8);
+      return {t.x, -t.y};
+    } else {
+      return buf_ld2(tinv, (unsigned)n1 * 8u, (c1 * Mb + Ma * qq) * 8);
+    }
+  };
   cf v[Mb];
   // staged blocks: line ranks of the block's 2G lines (slot sl of the tile)
   auto slot_line = [&](int sl, int& rank, bool& ok, bool dst_side) {
@@ -423,8 +481,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const int ub = MIR ? (Ma - 1 - n1) + Ma * (Mb - 1 - k) : ua;
       const float av = stg[ua * SP + sa], bv = stg[ub * SP + sb];
       const float sc = n2 < Mb / 2 ? sg : 1.0f;
-      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
-      v[n2] = cmul({sc * av, sc * bv}, w);
+      const cf w = tw_fold(n2);
+      v[n2] = cmul_1p({sc * av, sc * bv}, w);
     }
     __syncthreads();      // the tile is free: exchanges may overwrite it
   } else if constexpr (fast && (IO == kIoWinWin || IO == kIoWinFull)) {
@@ -439,8 +497,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const int sb = (int)off_src(MIR ? Ma * (Mb - 1 - k) : Ma * k);
       const float av = buf_ld<kLdPol>(srcA, la_lane, sa), bv = buf_ld<kLdPol>(srcB, lb_lane, sb);
       const float sc = n2 < Mb / 2 ? sg : 1.0f;    // the valid candidate is n = m + M below Mb/2
-      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
-      v[n2] = cmul({sc * av, sc * bv}, w);
+      const cf w = tw_fold(n2);
+      v[n2] = cmul_1p({sc * av, sc * bv}, w);
     }
   } else if constexpr (fast && IO == kIoFullWin) {
     // support [0, P): both candidates n = m and n = m + M are valid
@@ -453,8 +511,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
       const int sb1 = (int)off_src(MIR ? Ma * (Mb - 1 - n2) : Ma * n2 + M);
       const float a0 = buf_ld<kLdPol>(srcA, la_lane, sa0), a1 = buf_ld<kLdPol>(srcA, la_lane, sa1);
       const float b0 = buf_ld<kLdPol>(srcB, lb_lane, sb0), b1 = buf_ld<kLdPol>(srcB, lb_lane, sb1);
-      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
-      v[n2] = cmul({fmaf(sg, a1, a0), fmaf(sg, b1, b0)}, w);
+      const cf w = tw_fold(n2);
+      v[n2] = cmul_1p({fmaf(sg, a1, a0), fmaf(sg, b1, b0)}, w);
     }
   } else {
 #pragma unroll
@@ -472,8 +530,8 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
         const unsigned ob = in ? base_b + off_src((int)pb) : kOOB;
         z[cnd] = {buf_ld<kLdPol>(srcA, oa), buf_ld<kLdPol>(srcB, ob)};
       }
-      const cf w = buf_ld2(tfold, tw_lane, Ma * n2 * 8);
-      v[n2] = cmul({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
+      const cf w = tw_fold(n2);
+      v[n2] = cmul_1p({fmaf(sg, z[1].x, z[0].x), fmaf(sg, z[1].y, z[0].y)}, w);
     }
   }
 
@@ -482,7 +540,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // ---- step A: length-Mb transforms over n2, twiddle ----
   Dft<Mb, -1>::run(v);
 #pragma unroll
-  for (int k2 = 0; k2 < Mb; ++k2) v[k2] = cmul(v[k2], buf_ld2(tfwd, (unsigned)n1 * 8u, k2 * Ma * 8));
+  for (int k2 = 0; k2 < Mb; ++k2) v[k2] = cmul(v[k2], tw_fwd(k2));
 
   // ---- exchange 1 (real parts, then imaginary parts) ----
   constexpr int NQ = Mb / Ma;
@@ -529,7 +587,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
     }
     Dft<Ma, +1>::run(w);
 #pragma unroll
-    for (int c1 = 0; c1 < Ma; ++c1) w[c1] = cmul(w[c1], buf_ld2(tinv, (unsigned)n1 * 8u, (c1 * Mb + Ma * qq) * 8));
+    for (int c1 = 0; c1 < Ma; ++c1) w[c1] = cmul(w[c1], tw_inv(c1, qq));
   }
 
   // ---- exchange 2 ----
@@ -568,7 +626,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // value X (e, or W o) to the other and forms y = sg * X_own + X_other, whose
   // real part is line a and imaginary part line b' at position n = m + h M. ----
 #pragma unroll
-  for (int n2 = 0; n2 < Mb; ++n2) v[n2] = cmulc(v[n2], buf_ld2(tfold, tw_lane, Ma * n2 * 8));
+  for (int n2 = 0; n2 < Mb; ++n2) v[n2] = cmulc_1p(v[n2], tw_fold(n2));
 
   const int dst_lo = p.dst_line_lo + (p.flip_lines ? flipf : 0);
   const unsigned dls4 = (unsigned)p.dst_ls * 4u;
@@ -1092,6 +1150,24 @@ constexpr bool staged() {
   return GRAPHIC_COL_STAGED && KIND == kColPass && IO == kIoWinWin && lanes_on_jobs<KIND>();
 }
 
+// Block slot lb of a pass -> frame f and block jb of that frame (with frame
+// groups: frame fastest inside each group of p.frame_group frames).
+__device__ __forceinline__ void slot_frame_block(const LinePass& p, unsigned lb, unsigned& f, unsigned& jb) {
+  const unsigned bpf = (unsigned)p.blocks_per_frame;
+  if (p.frame_group > 1) {
+    const unsigned fg = (unsigned)p.frame_group;
+    const unsigned grp = lb / (fg * bpf);
+    const unsigned rem = lb - grp * (fg * bpf);
+    const unsigned f0 = grp * fg;
+    const unsigned cnt = min(fg, (unsigned)p.n_frames - f0);
+    jb = rem / cnt;
+    f = f0 + (rem - jb * cnt);
+  } else {
+    f = lb / bpf;
+    jb = lb - f * bpf;
+  }
+}
+
 // Canonical-geometry and general kernels over a regular grid.  The hardware
 // deals consecutive block ids to the eight XCDs in turn; the remap gives each
 // XCD a contiguous range of blocks, so neighbouring lines share its L2.  When
@@ -1111,23 +1187,64 @@ line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
   const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-  const unsigned bpf = (unsigned)p.blocks_per_frame;
   unsigned f, jb;
-  if (p.frame_group > 1) {
-    const unsigned fg = (unsigned)p.frame_group;
-    const unsigned grp = lb / (fg * bpf);
-    const unsigned rem = lb - grp * (fg * bpf);
-    const unsigned f0 = grp * fg;
-    const unsigned cnt = min(fg, (unsigned)p.n_frames - f0);
-    jb = rem / cnt;
-    f = f0 + (rem - jb * cnt);
-  } else {
-    f = lb / bpf;
-    jb = lb - f * bpf;
-  }
+  slot_frame_block(p, lb, f, jb);
   if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
     return;   // whole block leaves together, before any barrier
   process_block<M, KIND, G, IO, MIR, staged<KIND, IO>(), TM>(p, f, jb);
+}
+
+// ---------------------------------------------------------------------------
+// Row passes at M = 1024 with the twiddle tables in LDS.
+//
+// Every job of a pass multiplies by the same twiddle factors: the fold /
+// unfold factors (2M complex values) and the forward four-step factors (M;
+// the inverse ones are their conjugates).  Read from the global tables, each
+// one-wave job issues 128 table loads (tens of KiB) through the vector memory
+// path, and the transform stalls on their latency between its stages.  With
+// the loads removed altogether (wrong results, timing only) the five line
+// passes ran 12 of 48 ms faster per 2048 frames of 1024^2.  Here a block of
+// kRowLdsWaves waves copies the 24 KiB of tables into LDS once; after that
+// single barrier every wave walks its own sequence of slots (slot = frame and
+// job, ordered as the blocks of line_pass_kernel) with its own exchange area,
+// so the waves of a compute unit drift apart and overlap their loads with
+// each other's arithmetic.  Sixteen exchange areas and the tables take the
+// whole 160 KiB of LDS: one block per compute unit, four waves per SIMD.
+// Slots s of XCD x (block b = x + 8 i) are the contiguous run of that XCD.
+// Measured per 2048 frames of 1024^2: the first x-shear 8.85 -> 7.37 ms; the
+// shift's row pass and the last x-shear gained at most 0.3 ms and the pass
+// after them lost as much, so by default only the first x-shear runs here.
+// (Staged column blocks of 16 jobs with the tables in LDS, one block per
+// compute unit, were slower: shift_y 7.1 -> 8.6 ms, shear_y 16.2 -> 16.6.)
+// ---------------------------------------------------------------------------
+constexpr int kRowLdsM = 1024;
+constexpr int kRowLdsWaves = 16;
+constexpr int row_lds_wave_floats() { return lds_floats<kRowLdsM, kRowPass, 1, false>(); }
+constexpr int row_lds_floats() { return kRowLdsWaves * row_lds_wave_floats() + 3 * kRowLdsM * 2; }
+
+template <int IO, bool MIR, int TM>
+__global__ void __launch_bounds__(kRowLdsWaves * 64)
+line_pass_rows_lds_kernel(const LinePass p) {
+  constexpr int M = kRowLdsM;
+  extern __shared__ float lds_raw[];
+  // 8-byte aligned pairs: one 64-bit LDS read per factor
+  float2* lfold = reinterpret_cast<float2*>(lds_raw + kRowLdsWaves * row_lds_wave_floats());
+  float2* lfwd = lfold + 2 * M;
+  for (int i = threadIdx.x; i < 3 * M; i += kRowLdsWaves * 64) lfold[i] = i < 2 * M ? p.tw.fold[i] : p.tw.fwd[i - 2 * M];
+  __syncthreads();
+  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float* wlds = lds_raw + wave * row_lds_wave_floats();
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned lb = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const unsigned long long n_slots = (unsigned long long)p.n_frames * (unsigned)p.blocks_per_frame;
+  const unsigned long long stride = (unsigned long long)nb * kRowLdsWaves;
+  for (unsigned long long s = (unsigned long long)lb * kRowLdsWaves + wave; s < n_slots; s += stride) {
+    unsigned f, jb;
+    slot_frame_block(p, (unsigned)s, f, jb);
+    if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
+      continue;   // half-turned frames take line_pass_flipped_kernel
+    process_block<M, kRowPass, 1, IO, MIR, false, TM, true>(p, f, jb, wlds, lfold, lfwd);
+  }
 }
 
 // General path for the half-turned frames listed in p.flip_list (count in
@@ -1147,6 +1264,20 @@ line_pass_flipped_kernel(const LinePass p) {
 // ---------------------------------------------------------------------------
 // Launch
 // ---------------------------------------------------------------------------
+
+// Compute units of the current device (persistent launches size their grid
+// to it); cached per device.
+static int compute_units() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n <= 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+  }
+  return n;
+}
 
 template <int M>
 constexpr int col_jobs_per_block() {
@@ -1177,11 +1308,21 @@ static hipError_t launch_g(LinePass p, hipStream_t st) {
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool flipped = IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse);
   if ((TM & 2) && flipped) return hipErrorInvalidValue;   // the general path stores frame-major only
-  const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
-  hipError_t e = set_dynamic_lds(line_pass_kernel<M, KIND, G, IO, MIR, TM>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR, TM>), dim3((unsigned)blocks), dim3(G * S::JOB), lds, st,
-                     p);
+  hipError_t e;
+  if constexpr (KIND == kRowPass && M == kRowLdsM && G == 1 && IO != kIoGeneric &&
+                ((GRAPHIC_ROW_LDS_TW >> (IO - 1)) & 1)) {
+    constexpr size_t lds = (size_t)row_lds_floats() * sizeof(float);
+    static_assert(lds <= 160 * 1024, "LDS per block above 160 KiB");
+    if ((e = set_dynamic_lds(line_pass_rows_lds_kernel<IO, MIR, TM>, lds)) != hipSuccess) return e;
+    const long long grid = std::min<long long>((blocks + kRowLdsWaves - 1) / kRowLdsWaves, compute_units());
+    hipLaunchKernelGGL((line_pass_rows_lds_kernel<IO, MIR, TM>), dim3((unsigned)grid), dim3(kRowLdsWaves * 64), lds,
+                       st, p);
+  } else {
+    const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
+    if ((e = set_dynamic_lds(line_pass_kernel<M, KIND, G, IO, MIR, TM>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR, TM>), dim3((unsigned)blocks), dim3(G * S::JOB), lds,
+                       st, p);
+  }
   e = hipGetLastError();
   if (e != hipSuccess || !flipped) return e;
   // half-turned frames: general path over the device-side list
