@@ -135,10 +135,10 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 #endif
 // Row passes at M = 1024 that read their twiddle factors from LDS
 // (persistent blocks of 16 waves) instead of the global tables, by index
-// pattern: bit 0 window to window, bit 1 window to full line (the first
-// x-shear, the measured gain), bit 2 full line to window.
+// pattern: bit 0 window to window (the shift's row pass), bit 1 window to
+// full line (first x-shear), bit 2 full line to window (last x-shear).
 #ifndef GRAPHIC_ROW_LDS_TW
-#define GRAPHIC_ROW_LDS_TW 2
+#define GRAPHIC_ROW_LDS_TW 6
 #endif
 #ifndef GRAPHIC_COL_WAVE_LAYOUT
 #define GRAPHIC_COL_WAVE_LAYOUT 0
@@ -179,11 +179,14 @@ constexpr int waves_per_eu() {
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 
-// Cache policy of the frame loads: the x-shears read their frames with the
-// non-temporal hint (each value is read once, and the twiddle tables then
-// stay cached: measured 0.3-0.6 ms faster per 2048 frames of 1024^2); the
-// y-shear, which writes back the lines it reads, and the shift passes were
-// measured slower or unchanged with it and keep the default.
+// Cache policy of the frame loads: the x-shears that read their twiddle
+// factors from the global tables read their frames with the non-temporal
+// hint (each value is read once, and the tables then stay cached: measured
+// 0.3-0.6 ms faster per 2048 frames of 1024^2); the y-shear, which writes back
+// the lines it reads, and the shift passes were measured slower or unchanged
+// with it and keep the default.  With the tables in LDS the default policy is
+// faster (first x-shear 7.35 -> 6.11 ms per 2048 frames of 1024^2): the waves
+// that share a 128-byte line of the tile-major stack then find it in L2.
 constexpr int kCpolDefault = 0;
 constexpr int kCpolNonTemporal = 2;
 #ifndef GRAPHIC_PRIO_ALL
@@ -245,13 +248,15 @@ constexpr int lds_floats() {
 // row of the frame is then M / 16 chunks of 16 pixels, cs = 64 T bytes apart,
 // and each of the job's two rows gets its own wave-uniform descriptor (row
 // passes with M >= 1024 run one job per wave).
-template <int M, int KIND, int G, int IO, bool MIR, bool STG = false, int TM = 0, bool TWL = false>
+template <int M, int KIND, int G, int IO, bool MIR, bool STG = false, int TM = 0, int TWL = 0>
 __device__ __forceinline__ void process_block(const LinePass& p, const unsigned f, const unsigned jb,
                                               float* wlds = nullptr, const float2* lfold = nullptr,
                                               const float2* lfwd = nullptr) {
   using S = Shape<M>;
   constexpr int Ma = S::Ma, Mb = S::Mb, JOB = S::JOB;
-  static_assert(!TWL || (KIND == kRowPass && G == 1 && JOB == 64 && Ma == Mb && !STG),
+  // TWL: 0 twiddles from the global tables; 1 fold and forward tables in LDS
+  // (one-wave row jobs, each with its own LDS area)
+  static_assert(TWL == 0 || (TWL == 1 && Ma == Mb && KIND == kRowPass && G == 1 && JOB == 64 && !STG),
                 "LDS twiddles: one-wave row jobs of a square four-step split");
   static_assert(!STG || (KIND == kColPass && IO == kIoWinWin), "staging covers the window-to-window column pass");
   constexpr bool TMS = (TM & 1) != 0, TMD = (TM & 2) != 0;
@@ -267,13 +272,12 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   constexpr int BUF = G * 2 * S::HALF;
   constexpr int SP = 2 * G + 1;                        // staging tile pitch (floats per row)
   extern __shared__ float lds_raw[];
-  // TWL: twiddles in LDS, and the wave's own exchange area and phasor table
-  // (wlds)
-  float* lds = TWL ? wlds : lds_raw;
+  // TWL == 1: the wave's own exchange area and phasor table (wlds)
+  float* lds = TWL == 1 ? wlds : lds_raw;
   float* stg = lds_raw;                                // staging tile (aliases the exchange buffers)
   cf* ptab = reinterpret_cast<cf*>(lds + (lds_floats<M, KIND, G, STG>() - 2 * G * Ma));
 
-  const int tid = TWL ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+  const int tid = TWL == 1 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
   int jl, r;
   if constexpr (!LJ) {
     jl = tid / JOB;
@@ -400,7 +404,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // requests are in flight early; measured per pass: it helps the shift
   // passes and the first shear, and slows the y-shear and the last shear.
   constexpr bool kLoadPrio = GRAPHIC_PRIO_ALL || (!(KIND == kColPass && MIR) && IO != kIoFullWin);
-  constexpr int kLdPol = (KIND == kRowPass && MIR) ? kCpolNonTemporal : kCpolDefault;
+  constexpr int kLdPol = (KIND == kRowPass && MIR && TWL == 0) ? kCpolNonTemporal : kCpolDefault;
   if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(2);
 
   // ---- load, pack and fold into this half's branch ----
@@ -410,24 +414,24 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // Ma n2 of half h; the even half reads out of bounds, d = 0, and fetches
   // nothing), forward four-step (n1 k2), inverse four-step (the conjugate of
   // the forward factor at (c1, n1) when Ma == Mb, so both read one table);
-  // from LDS when TWL
+  // from LDS as TWL selects
   const unsigned tw_fold_lane = h ? tw_lane : kOOB;
   auto tw_fold = [&](int n2) -> cf {
-    if constexpr (TWL) {
+    if constexpr (TWL == 1) {
       const float2 t = lfold[h * M + n1 + Ma * n2];
       return {t.x, t.y};
     }
     else return buf_ld2(tfold, tw_fold_lane, Ma * n2 * 8);
   };
   auto tw_fwd = [&](int k2) -> cf {
-    if constexpr (TWL) {
+    if constexpr (TWL != 0) {
       const float2 t = lfwd[n1 + Ma * k2];
       return {t.x, t.y};
     }
     else return buf_ld2(tfwd, (unsigned)n1 * 8u, k2 * Ma * 8);
   };
   auto tw_inv = [&](int c1, int qq) -> cf {
-    if constexpr (TWL) {
+    if constexpr (TWL != 0) {
       const float2 t = lfwd[n1 + Ma * c1];
       return {t.x, -t.y};
     } else if constexpr (Ma == Mb) {
@@ -1211,11 +1215,12 @@ line_pass_kernel(const LinePass p) {
 // each other's arithmetic.  Sixteen exchange areas and the tables take the
 // whole 160 KiB of LDS: one block per compute unit, four waves per SIMD.
 // Slots s of XCD x (block b = x + 8 i) are the contiguous run of that XCD.
-// Measured per 2048 frames of 1024^2: the first x-shear 8.85 -> 7.37 ms; the
-// shift's row pass and the last x-shear gained at most 0.3 ms and the pass
-// after them lost as much, so by default only the first x-shear runs here.
-// (Staged column blocks of 16 jobs with the tables in LDS, one block per
-// compute unit, were slower: shift_y 7.1 -> 8.6 ms, shear_y 16.2 -> 16.6.)
+// Measured per 2048 frames of 1024^2 (with the default cache policy, see
+// kLdPol): first x-shear 8.85 -> 6.1 ms, last x-shear 8.9 -> 8.45 ms; the
+// shift's row pass gained nothing and keeps the global tables.  Staged column
+// blocks of 16 jobs with the tables in LDS (one block per compute unit) were
+// slower (shift_y 7.1 -> 8.6 ms, shear_y 16.2 -> 16.6), and the forward table
+// alone in LDS beside the tile of 8 jobs changed nothing.
 // ---------------------------------------------------------------------------
 constexpr int kRowLdsM = 1024;
 constexpr int kRowLdsWaves = 16;
@@ -1243,7 +1248,7 @@ line_pass_rows_lds_kernel(const LinePass p) {
     slot_frame_block(p, (unsigned)s, f, jb);
     if (IO != kIoGeneric && p.flip != nullptr && (p.flip_in_off || p.flip_src_reverse) && p.flip[f] != 0)
       continue;   // half-turned frames take line_pass_flipped_kernel
-    process_block<M, kRowPass, 1, IO, MIR, false, TM, true>(p, f, jb, wlds, lfold, lfwd);
+    process_block<M, kRowPass, 1, IO, MIR, false, TM, 1>(p, f, jb, wlds, lfold, lfwd);
   }
 }
 
@@ -1318,7 +1323,7 @@ static hipError_t launch_g(LinePass p, hipStream_t st) {
     hipLaunchKernelGGL((line_pass_rows_lds_kernel<IO, MIR, TM>), dim3((unsigned)grid), dim3(kRowLdsWaves * 64), lds,
                        st, p);
   } else {
-    const size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
+    constexpr size_t lds = (size_t)lds_floats<M, KIND, G, staged<KIND, IO>()>() * sizeof(float);
     if ((e = set_dynamic_lds(line_pass_kernel<M, KIND, G, IO, MIR, TM>, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL((line_pass_kernel<M, KIND, G, IO, MIR, TM>), dim3((unsigned)blocks), dim3(G * S::JOB), lds,
                        st, p);
