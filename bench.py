@@ -686,7 +686,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the cube (known bytes) before the timed steps, "
                          "to scale hardware byte counters")
-    ap.add_argument("--traffic", default=os.path.join(HERE, "profiles", "traffic_adi_1024.txt"))
+    ap.add_argument("--traffic", default=None,
+                    help="calibrated counter record (default: profiles/traffic_adi_<N>.txt)")
     ap.add_argument("--verify-frames", type=int, default=8,
                     help="sampled frames checked against the oracle after the timed steps (0: none)")
     args = ap.parse_args()
@@ -793,7 +794,8 @@ def main():
             d["achieved_TFLOPs"] = d["alg_flops_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e12
     dom = max((f for f in fams if "achieved_GBps" in fams[f]), key=lambda f: fams[f]["ms_per_step"])
     traffic = None
-    per_frame = read_traffic(args.traffic, dom, N, P)
+    tpath = args.traffic or os.path.join(HERE, "profiles", "traffic_adi_%d.txt" % N)
+    per_frame = read_traffic(tpath, dom, N, P)
     if per_frame is not None:
         traffic = round(per_frame * T / fams[dom]["launches_per_step"])
     sl = sorted(step_ms)

@@ -889,7 +889,11 @@ void* scratch_ptr(int dev) {
 extern "C" {
 
 const char* graphic_status_string(graphic_status s) {
-  switch (s) {
+  // C callers may pass any int: read the bits as int, since a value outside
+  // the enumerators is not a valid value of the C++ enum type
+  int v;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case GRAPHIC_OK: return "GRAPHIC_OK";
     case GRAPHIC_ERR_ARG: return "GRAPHIC_ERR_ARG: invalid argument";
     case GRAPHIC_ERR_UNSUPPORTED: return "GRAPHIC_ERR_UNSUPPORTED: unsupported geometry";
