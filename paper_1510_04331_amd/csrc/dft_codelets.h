@@ -149,14 +149,69 @@ struct Dft<4, SIGN> {
   }
 };
 
+// Twiddle with a deferred scale: exp(SIGN * 2*pi*i * E / L) = scale * (1 + i r)
+// or scale * (r + i), so a * twiddle = scale * apply(a) where apply costs two
+// fused multiply-adds (or two additions for the odd octants, nothing for
+// quarter turns).  The compile-time scale is left to the caller, who folds it
+// into the additions of the next butterfly (x + scale * y is one FMA), which
+// saves the two multiplications of a plain complex product.
+template <long E, long L, int SIGN>
+struct ScaledTwiddle {
+  static constexpr long e = ((E % L) + L) % L;
+  static constexpr bool trivial = e == 0 || (4 * e) % L == 0;
+  static constexpr bool octant = !trivial && (8 * e) % L == 0;
+  static constexpr double c = ct::cs(e, L, 0);
+  static constexpr double sn = SIGN * ct::cs(e, L, 1);
+  static constexpr bool cos_major = (c < 0 ? -c : c) >= (sn < 0 ? -sn : sn);
+  // the scale, in double (its float rounding is taken where it is used)
+  static constexpr double scale_d = trivial ? 1.0
+                                    : octant ? 0.70710678118654752440
+                                             : (cos_major ? c : sn);
+  static __device__ __forceinline__ cf apply(cf a) {
+    if constexpr (trivial) {
+      return twiddle<E, L, SIGN>(a);
+    } else if constexpr (octant) {
+      constexpr long o = (8 * e) / L;            // odd octant 1,3,5,7
+      constexpr long os = SIGN > 0 ? o : (8 - o);
+      constexpr float cx = (os == 1 || os == 7) ? 1.0f : -1.0f;
+      constexpr float sy = (os == 1 || os == 3) ? 1.0f : -1.0f;
+      return {cx * a.x - sy * a.y, cx * a.y + sy * a.x};
+    } else if constexpr (cos_major) {
+      constexpr float r = (float)(sn / c);       // |r| <= 1
+      return {fmaf(-a.y, r, a.x), fmaf(a.x, r, a.y)};
+    } else {
+      constexpr float r = (float)(c / sn);       // |r| < 1
+      return {fmaf(a.x, r, -a.y), fmaf(a.y, r, a.x)};
+    }
+  }
+};
+
 namespace detail {
+// One radix-4 butterfly of the decimation in time, with the three twiddles'
+// scales folded into its additions: with b_k = c_k u_k (c_0 = 1),
+//   t0, t1 = b0 +- c2 u2;  t2 = c1 (u1 + (c3/c1) u3);  t3 = c1 (u1 - (c3/c1) u3) (-+i)
+// and every output is t0 or t1 plus or minus c1 times a term: twelve fused
+// multiply-adds or additions per component pair, as the plain butterfly.
 template <int L, int SIGN, int Q, int K>
 __device__ __forceinline__ void combine4(cf (&s)[4][Q], cf* v) {
-  cf b0 = s[0][K];
-  cf b1 = twiddle<K, L, SIGN>(s[1][K]);
-  cf b2 = twiddle<2 * K, L, SIGN>(s[2][K]);
-  cf b3 = twiddle<3 * K, L, SIGN>(s[3][K]);
-  radix4<SIGN>(b0, b1, b2, b3, v[K], v[K + Q], v[K + 2 * Q], v[K + 3 * Q]);
+  using T1 = ScaledTwiddle<K, L, SIGN>;
+  using T2 = ScaledTwiddle<2 * K, L, SIGN>;
+  using T3 = ScaledTwiddle<3 * K, L, SIGN>;
+  constexpr float c1 = (float)T1::scale_d;
+  constexpr float c2 = (float)T2::scale_d;
+  constexpr float r3 = (float)(T3::scale_d / T1::scale_d);
+  const cf b0 = s[0][K];
+  const cf u1 = T1::apply(s[1][K]);
+  const cf u2 = T2::apply(s[2][K]);
+  const cf u3 = T3::apply(s[3][K]);
+  const cf t0 = {fmaf(c2, u2.x, b0.x), fmaf(c2, u2.y, b0.y)};
+  const cf t1 = {fmaf(-c2, u2.x, b0.x), fmaf(-c2, u2.y, b0.y)};
+  const cf p = {fmaf(r3, u3.x, u1.x), fmaf(r3, u3.y, u1.y)};
+  const cf m = mul_i<SIGN>(cf{fmaf(-r3, u3.x, u1.x), fmaf(-r3, u3.y, u1.y)});
+  v[K] = {fmaf(c1, p.x, t0.x), fmaf(c1, p.y, t0.y)};
+  v[K + 2 * Q] = {fmaf(-c1, p.x, t0.x), fmaf(-c1, p.y, t0.y)};
+  v[K + Q] = {fmaf(c1, m.x, t1.x), fmaf(c1, m.y, t1.y)};
+  v[K + 3 * Q] = {fmaf(-c1, m.x, t1.x), fmaf(-c1, m.y, t1.y)};
 }
 template <int L, int SIGN, int Q, int... Ks>
 __device__ __forceinline__ void combine4_all(cf (&s)[4][Q], cf* v, std::integer_sequence<int, Ks...>) {
