@@ -76,11 +76,13 @@ struct graphic_ctx_s {
   size_t chunk_bytes = kDefaultChunkBytes;
   bool tile_major = true;                 // workspace stacks of the large canonical sizes are tile-major
   // Block order of the row passes over tile-major stacks: blocks of this many
-  // consecutive frames are interleaved.  The x-shears, whose other side is a
-  // frame-major scratch, take smaller groups: with 64 they ran at one of two
-  // speeds from process to process, with 32 always at the faster one.
+  // consecutive frames are interleaved.  The x-shears run as persistent
+  // blocks whose 16 waves take 16 consecutive slots; with the whole launch as
+  // one group (frame fastest throughout) they were fastest: per 2048 frames
+  // of 1024^2, 6.15 + 8.22 ms with groups of 32, 5.86 + 7.94 ms with all
+  // frames.  The shift's row pass (one-wave blocks) keeps 64.
   int frame_group = 64;                   // the shift's row pass
-  int frame_group_shear = 32;             // the two x-shears
+  int frame_group_shear = 4096;           // the two x-shears
   // tuned launch variants (-1: not tuned, the default variant 0 runs)
   int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass
   int med_var[8];                         // [log2 of the median's values per thread]
@@ -928,6 +930,10 @@ graphic_status graphic_create(graphic_ctx* out, int hip_device) {
   if (const char* env = std::getenv("GRAPHIC_FRAME_GROUP")) {   // every row pass
     const int v = std::atoi(env);
     if (v >= 1 && v <= 4096) c->frame_group = c->frame_group_shear = v;
+  }
+  if (const char* env = std::getenv("GRAPHIC_FRAME_GROUP_SHEAR")) {   // the two x-shears
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 4096) c->frame_group_shear = v;
   }
   graphic_status s = build_tables(c);
   if (s != GRAPHIC_OK) {
