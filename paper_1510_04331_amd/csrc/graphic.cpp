@@ -80,8 +80,9 @@ struct graphic_ctx_s {
   // blocks whose 16 waves take 16 consecutive slots; with the whole launch as
   // one group (frame fastest throughout) they were fastest: per 2048 frames
   // of 1024^2, 6.15 + 8.22 ms with groups of 32, 5.86 + 7.94 ms with all
-  // frames.  The shift's row pass (one-wave blocks) keeps 64.
-  int frame_group = 64;                   // the shift's row pass
+  // frames.  The shift's row pass also gains a little (6.89 -> 6.81 ms
+  // against groups of 64).
+  int frame_group = 4096;                 // the shift's row pass
   int frame_group_shear = 4096;           // the two x-shears
   // tuned launch variants (-1: not tuned, the default variant 0 runs)
   int col_var[16][2];                     // [log2 M][pairing: 0 same, 1 mirror] of the staged column pass

@@ -129,9 +129,10 @@ __device__ __forceinline__ cf phase_exp(double kk, double q, float scale) {
 #ifndef GRAPHIC_COL_DB_2048
 #define GRAPHIC_COL_DB_2048 0
 #endif
-// Occupancy target (waves per SIMD) of the same-pair row pass at M = 1024.
+// Occupancy target (waves per SIMD) of the same-pair row pass at M = 1024
+// (canonical window).
 #ifndef GRAPHIC_ROW_W_1024
-#define GRAPHIC_ROW_W_1024 3
+#define GRAPHIC_ROW_W_1024 4
 #endif
 // Row passes at M = 1024 that read their twiddle factors from LDS
 // (persistent blocks of 16 waves) instead of the global tables, by index
@@ -165,7 +166,7 @@ constexpr bool col_db() {
           : M == 2048 ? GRAPHIC_COL_DB_2048 : 1);
 }
 
-template <int M, int KIND, bool MIR = false>
+template <int M, int KIND, bool MIR = false, int IO = kIoWinWin>
 constexpr int waves_per_eu() {
   if (KIND == kColPass && lanes_on_jobs<KIND>()) {
     if (M == 256) return GRAPHIC_COL_W_256;
@@ -173,8 +174,11 @@ constexpr int waves_per_eu() {
     if (M == 1024) return GRAPHIC_COL_W_1024;
     if (M == 2048) return GRAPHIC_COL_W_2048;
   }
-  // rows of M = 1024: the mirror-paired shears fit 4 waves without spilling
-  return M <= 256 ? 4 : (M == 1024 ? (MIR ? 4 : GRAPHIC_ROW_W_1024) : 2);
+  // rows of M = 1024: the mirror-paired shears fit 4 waves without spilling;
+  // the same-pair pass of the canonical window spills one value at 4 and is
+  // still faster there (6.89 -> 6.75 ms per 2048 frames of 1024^2); its
+  // general index path would spill 8 and keeps 3
+  return M <= 256 ? 4 : (M == 1024 ? (MIR ? 4 : (IO == kIoGeneric ? 3 : GRAPHIC_ROW_W_1024)) : 2);
 }
 
 typedef int v2i __attribute__((ext_vector_type(2)));
@@ -1186,7 +1190,7 @@ __device__ __forceinline__ void slot_frame_block(const LinePass& p, unsigned lb,
 // 64-byte pieces of one run.
 template <int M, int KIND, int G, int IO, bool MIR, int TM>
 __global__ void __launch_bounds__(G * Shape<M>::JOB)
-__attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND, MIR>(), waves_per_eu<M, KIND, MIR>())))
+__attribute__((amdgpu_waves_per_eu(waves_per_eu<M, KIND, MIR, IO>(), waves_per_eu<M, KIND, MIR, IO>())))
 line_pass_kernel(const LinePass p) {
   const unsigned nb = gridDim.x;
   const unsigned b = blockIdx.x;
@@ -1255,7 +1259,7 @@ line_pass_rows_lds_kernel(const LinePass p) {
 // General path for the half-turned frames listed in p.flip_list (count in
 // p.flip_count): a fixed grid walks the (frame, block) pairs.
 template <int M, int KIND, int G, bool MIR, int TM>
-__global__ void __launch_bounds__(G * Shape<M>::JOB, (waves_per_eu<M, KIND>()))
+__global__ void __launch_bounds__(G * Shape<M>::JOB, (waves_per_eu<M, KIND, false, kIoGeneric>()))
 line_pass_flipped_kernel(const LinePass p) {
   const unsigned bpf = (unsigned)p.blocks_per_frame;
   const unsigned work = (unsigned)(*p.flip_count) * bpf;
