@@ -188,9 +188,11 @@ typedef int v2i __attribute__((ext_vector_type(2)));
 // hint (each value is read once, and the tables then stay cached: measured
 // 0.3-0.6 ms faster per 2048 frames of 1024^2); the y-shear, which writes back
 // the lines it reads, and the shift passes were measured slower or unchanged
-// with it and keep the default.  With the tables in LDS the default policy is
-// faster (first x-shear 7.35 -> 6.11 ms per 2048 frames of 1024^2): the waves
-// that share a 128-byte line of the tile-major stack then find it in L2.
+// with it and keep the default.  With the tables in LDS the first x-shear is
+// faster with the default policy (7.35 -> 6.11 ms per 2048 frames of
+// 1024^2): the waves that share a 128-byte line of the tile-major stack then
+// find it in L2; the last x-shear, which reads whole frame-major lines once,
+// keeps the hint (8.0 -> 7.64 ms).
 constexpr int kCpolDefault = 0;
 constexpr int kCpolNonTemporal = 2;
 #ifndef GRAPHIC_PRIO_ALL
@@ -408,7 +410,7 @@ __device__ __forceinline__ void process_block(const LinePass& p, const unsigned 
   // requests are in flight early; measured per pass: it helps the shift
   // passes and the first shear, and slows the y-shear and the last shear.
   constexpr bool kLoadPrio = GRAPHIC_PRIO_ALL || (!(KIND == kColPass && MIR) && IO != kIoFullWin);
-  constexpr int kLdPol = (KIND == kRowPass && MIR && TWL == 0) ? kCpolNonTemporal : kCpolDefault;
+  constexpr int kLdPol = (KIND == kRowPass && MIR && (TWL == 0 || IO == kIoFullWin)) ? kCpolNonTemporal : kCpolDefault;
   if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(2);
 
   // ---- load, pack and fold into this half's branch ----
