@@ -8,7 +8,7 @@ SPHERE-like cube of 4096 frames of 1024 x 1024 float32 (zero-padded to
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Two more workloads print their own JSON line:
+Other workloads print their own JSON line:
 
     python bench.py --workload batch    64 uneven cubes (T log-uniform in
         [32, 2048], N in {256, 512, 1024, 2048}) reduced in place by one
@@ -18,6 +18,8 @@ Two more workloads print their own JSON line:
         streams), against one request at a time
     python bench.py --workload window   ADI with the per-frame PSF of the
         paper's frame selection, 1024 frames of 512^2
+    python bench.py --workload window_night  the same over a whole night,
+        16384 frames of 256^2 (the per-frame medians in row groups)
     python bench.py --workload register registration (centroid + Moffat fit)
         of 1024 frames of 512^2
     python bench.py --workload preprocess  pre-processing of Sect. 3.2 of
@@ -340,20 +342,30 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_window(args):
+def bench_window(args, night=False):
     """ADI with the per-frame PSF of the paper's frame selection on the
     NACO-like cube (1024 frames of 512^2): frames 2 s apart, angles spanning
     60 degrees, t_max = 1200 s, alpha_min = 2 arcsin(1 FWHM / (2 x 10 px)),
-    so each frame's PSF comes from the frames 23 to 35 degrees away."""
+    so each frame's PSF comes from the frames 23 to 35 degrees away.
+
+    night: a whole night instead, 16384 frames of 256^2 2 s apart (9.1 h),
+    angles spanning 180 degrees, t_max = 1200 s, alpha_min for 1 FWHM at
+    50 px (4.6 degrees); the per-frame medians then run in row groups."""
     import numpy as np
     import torch
     import paper_1510_04331_amd as G
     import synth
     dev = torch.device("cuda:0")
-    p = synth.make_params(2)
+    if night:
+        p = synth.make_params(2, T=16384, N=256)
+        p.parang = np.linspace(-90.0, 90.0, p.T)
+        r_min = 50.0
+    else:
+        p = synth.make_params(2)
+        r_min = 10.0
     cube = synth.render_device(p, dev)
     times = np.arange(p.T, dtype=np.float64) * 2.0
-    t_max, amin = 1200.0, G.alpha_min_deg(1.0, 4.0, 10.0)
+    t_max, amin = 1200.0, G.alpha_min_deg(1.0, 4.0, r_min)
     ws = torch.empty(G.workspace_size(5, p.T, p.N), dtype=torch.uint8, device=dev)
     G.autotune(p.T, p.N)
     for _ in range(args.warmup):
@@ -367,13 +379,20 @@ def bench_window(args):
     dt = (time.perf_counter() - t0) / args.steps
     med_ms, _ = G.timing_read("median")
     G.timing_enable(False)
-    sel = (np.abs(times[None, :] - times[:, None]) < t_max) & (np.abs(p.parang[None, :] - p.parang[:, None]) > amin)
+    sel_n = np.zeros(p.T)
+    for i0 in range(0, p.T, 1024):                        # selected frames per row, in slices of rows
+        rows = slice(i0, min(p.T, i0 + 1024))
+        sel_n[rows] = ((np.abs(times[None, :] - times[rows, None]) < t_max) &
+                       (np.abs(p.parang[None, :] - p.parang[rows, None]) > amin)).sum(axis=1)
     out = {"metric": "frames reduced/s, ADI with the per-frame PSF of the frame selection",
            "value": round(p.T / dt, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "NACO-like cube, 1024 frames of 512x512 (P = 1024), frames 2 s apart, "
-                                  "t_max 1200 s, alpha_min %.2f deg" % amin,
-                      "mean_selected_frames": round(float(sel.sum(axis=1).mean()), 1)},
+           "config": {"workload": "%s, %d frames of %dx%d (P = %d), frames 2 s apart, angles over %g deg, "
+                                  "t_max 1200 s, alpha_min %.2f deg"
+                                  % ("whole night" if night else "NACO-like cube", p.T, p.N, p.N, p.P,
+                                     float(p.parang[-1] - p.parang[0]), amin),
+                      "mean_selected_frames": round(float(sel_n.mean()), 1),
+                      "rows_selecting_nothing": int((sel_n == 0).sum())},
            "median_ms_per_step": round(med_ms / args.steps, 3)}
     print(json.dumps(out), flush=True)
 
@@ -671,8 +690,8 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "register", "preprocess", "quality",
-                                           "mfma"),
+    ap.add_argument("--workload", choices=("adi", "batch", "served", "window", "window_night", "register",
+                                           "preprocess", "quality", "mfma"),
                     default="adi")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip autotuning (default launch shapes; keeps tuning launches out of profiles)")
@@ -701,6 +720,8 @@ def main():
         return bench_served(args)
     if args.workload == "window":
         return bench_window(args)
+    if args.workload == "window_night":
+        return bench_window(args, night=True)
     if args.workload == "register":
         return bench_register(args)
     if args.workload == "quality":

@@ -238,7 +238,7 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
  * derive alpha_min_deg as the chord angle 2 arcsin(n FWHM / (2 r_min)).)
  * Frame i never selects itself unless alpha_min_deg < 0 or the fallback applies.
  * graphic_alpha_min_deg gives alpha_min_deg from the paper's parameters.
- *   stack     : [T][N][N] float32, T <= 2048.
+ *   stack     : [T][N][N] float32, T <= 262144.
  *   times     : [T] float64 observing times (any unit, the unit of t_max).
  *   parang_deg: [T] float64 parallactic angles.
  *   psf_cube  : NULL or [T][N][N] float32, receives PSF_i.
@@ -246,9 +246,19 @@ graphic_status graphic_adi_reduce(graphic_ctx ctx, const graphic_geom* geom,
  *               stack itself; otherwise it must not overlap it).  At least
  *               one of psf_cube and resid is given.
  *   ws        : graphic_workspace_size(GRAPHIC_OP_MEDIAN_WINDOW) bytes (the
- *               selection: T x 512 bytes plus T ints).
- * Cost: one sort of every pixel's T values, then per frame O(T / 64) work
- * per pixel plus the frames that enter or leave the selection.
+ *               selection: T x 512 bytes plus T ints; for T > 2048 also the
+ *               row-group plan, one [N][N] image and, for residuals written
+ *               with no PSF cube, 2304 [N][N] frames of PSF in waiting).
+ * Cost (T <= 2048): one sort of every pixel's T values, then per frame
+ * O(T / 64) work per pixel plus the frames that enter or leave the selection.
+ * Longer sequences (T > 2048) run in groups of 256 consecutive frames, each
+ * sorting only the frames its rows select; the call then waits once for the
+ * selection plan (a synchronisation of the stream) and returns
+ * GRAPHIC_ERR_UNSUPPORTED, before any output is written, when a group's
+ * frames select more than 2048 distinct frames, or, with resid given and
+ * psf_cube NULL, when a frame is selected by a frame of a group more than
+ * eight groups after its own (local windows, the paper's case, meet both).
+ * The plan compares every frame with every other, O(T^2).
  */
 graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, const float* stack,
                                      const double* times, const double* parang_deg, double t_max,
@@ -269,7 +279,8 @@ graphic_status graphic_alpha_min_deg(double n_fwhm, double fwhm, double r_min, d
  * ADI reduction with the per-frame PSF of graphic_median_window:
  * S_i = shift(cube_i), R_i = S_i - PSF_i, D_i = rotate(R_i, -parang_i),
  * final = median_i D_i.  Arguments as graphic_adi_reduce, plus the selection
- * (times, t_max, alpha_min_deg) and psf_cube (NULL or [T][N][N]).  T <= 2048.
+ * (times, t_max, alpha_min_deg) and psf_cube (NULL or [T][N][N]).  T <= 262144,
+ * with the same conditions for T > 2048 as graphic_median_window.
  *   ws : graphic_workspace_size(GRAPHIC_OP_ADI_WINDOW) bytes.
  */
 graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* geom, const float* cube,

@@ -42,7 +42,14 @@ constexpr size_t kAlign = 256;
 constexpr long long kMaxT_Median = 1LL << 24;
 constexpr int kMaxT_RegisterMedian = 4096;
 constexpr int kMaxT_NanMedian = 4096;
-constexpr int kMaxT_Window = 2048;      // the per-frame median keeps a median per held frame in registers
+// Per-frame medians of the selection window: up to kWinKeys frames one block
+// holds every value of its pixels; longer sequences run in row groups (each
+// group's selections must span at most kWinKeys frames), up to kMaxT_Window
+// frames (the plan compares every frame with every row).  With the residuals
+// written in place and no PSF cube, each group's PSF waits in a ring of
+// kWinRing groups until no later group reads the frames it overwrites.
+constexpr long long kMaxT_Window = 1LL << 18;
+constexpr int kWinRing = 9;
 constexpr size_t kDefaultChunkBytes = size_t(4) << 30;   // rotation scratch per chunk (fewer, fuller launches)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -204,9 +211,40 @@ graphic_status check_geom(const graphic_geom* g, int* P_out, uint32_t allowed = 
   return GRAPHIC_OK;
 }
 
-size_t window_sel_bytes(long long T) {
-  return align_up((size_t)T * 64 * sizeof(unsigned long long)) + align_up((size_t)T * sizeof(int));
+// Workspace of the per-frame medians: the selection rows and counts; for row
+// groups also the group lists, counts and last readers, the flags, the
+// all-frames median and the PSF ring.
+struct WindowLayout {
+  size_t sel = 0, counts = 0, list = 0, gcount = 0, need = 0, flags = 0, psf_all = 0, ring = 0, total = 0;
+};
+
+WindowLayout window_layout(long long T, long long npix) {
+  WindowLayout L;
+  size_t o = 0;
+  L.sel = o;
+  o += align_up((size_t)T * 64 * sizeof(unsigned long long));
+  L.counts = o;
+  o += align_up((size_t)T * sizeof(int));
+  if (T > kWinKeys) {
+    const size_t groups = (size_t)((T + kWinRows - 1) / kWinRows);
+    L.list = o;
+    o += align_up(groups * kWinKeys * sizeof(int));
+    L.gcount = o;
+    o += align_up(groups * sizeof(int));
+    L.need = o;
+    o += align_up(groups * sizeof(int));
+    L.flags = o;
+    o += kAlign;
+    L.psf_all = o;
+    o += align_up((size_t)npix * sizeof(float));
+    L.ring = o;
+    o += align_up((size_t)kWinRing * kWinRows * (size_t)npix * sizeof(float));
+  }
+  L.total = o;
+  return L;
 }
+
+size_t window_ws_bytes(long long T, long long npix) { return window_layout(T, npix).total; }
 
 bool overlap_bad(const void* a, const void* b, size_t bytes) {
   if (a == b) return false;
@@ -984,15 +1022,18 @@ graphic_status graphic_workspace_size(graphic_ctx ctx, int op, const graphic_geo
     }
     case GRAPHIC_OP_MEDIAN: *bytes = 0; return T > kMaxT_Median ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
     case GRAPHIC_OP_MEDIAN_WINDOW:
-      *bytes = window_sel_bytes(T);
-      return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+      if (T > kMaxT_Window) return GRAPHIC_ERR_UNSUPPORTED;
+      *bytes = window_ws_bytes(T, (long long)N * N);
+      return GRAPHIC_OK;
     case GRAPHIC_OP_BADPIX_MAP: *bytes = frame_stats_ws_bytes(); return GRAPHIC_OK;
     case GRAPHIC_OP_BADPIX_FIX:
       *bytes = align_up((size_t)T * N * N * sizeof(float)) + kAlign;
       return T > 65535 ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
     case GRAPHIC_OP_ADI_WINDOW:
-      *bytes = align_up((size_t)T * N * N * sizeof(float)) + window_sel_bytes(T) + rot_layout(T, N, P, chunk, 0).total;
-      return T > kMaxT_Window ? GRAPHIC_ERR_UNSUPPORTED : GRAPHIC_OK;
+      if (T > kMaxT_Window) return GRAPHIC_ERR_UNSUPPORTED;
+      *bytes = align_up((size_t)T * N * N * sizeof(float)) + window_ws_bytes(T, (long long)N * N) +
+               rot_layout(T, N, P, chunk, 0).total;
+      return GRAPHIC_OK;
     default: return GRAPHIC_ERR_ARG;
   }
 }
@@ -1153,13 +1194,80 @@ graphic_status window_args(graphic_ctx ctx, const graphic_geom* geom, const void
   return GRAPHIC_OK;
 }
 
-// Selection, then the per-frame medians (Sect. 3.3); sel_ws holds the
-// selection rows and counts.
+// Row groups of a long sequence (T > kWinKeys).  The plan is read back to the
+// host (one stream synchronisation): it rejects a group that selects more
+// than kWinKeys frames and, with the residuals written over the stack, fixes
+// when each group's residuals may be written: after the last group that
+// reads any of its frames.  A row that selects nothing takes the median of
+// all frames (computed only when such a row exists).
+graphic_status do_median_window_groups(graphic_ctx ctx, long long T, int N, const float* stack,
+                                       const double* times, const double* parang, double t_max, double alpha_min,
+                                       float* psf, float* resid, char* ws, hipStream_t st) {
+  const long long npix = (long long)N * N;
+  const WindowLayout L = window_layout(T, npix);
+  auto* sel = reinterpret_cast<unsigned long long*>(ws + L.sel);
+  int* list = reinterpret_cast<int*>(ws + L.list);
+  int* gcount = reinterpret_cast<int*>(ws + L.gcount);
+  int* need = reinterpret_cast<int*>(ws + L.need);
+  int* flags = reinterpret_cast<int*>(ws + L.flags);
+  float* psf_all = reinterpret_cast<float*>(ws + L.psf_all);
+  float* ring = reinterpret_cast<float*>(ws + L.ring);
+  const long long groups = (T + kWinRows - 1) / kWinRows;
+  std::vector<int> h_count((size_t)groups), h_need((size_t)groups);
+  int h_flags = 0;
+  {
+    Timer t(ctx, st, "aux");
+    hipError_t e = launch_window_plan(times, parang, T, t_max, alpha_min, list, gcount, need, sel, flags, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_count.data(), gcount, groups * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_need.data(), need, groups * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_flags, flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    t.done();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return GRAPHIC_ERR_HIP;
+  }
+  const bool in_place = resid == stack;
+  const bool use_ring = resid != nullptr && psf == nullptr;
+  // group g's residuals are written after group fin[g]
+  std::vector<std::vector<int>> write_after((size_t)groups);
+  for (long long g = 0; g < groups; ++g) {
+    if (h_count[g] > kWinKeys) return GRAPHIC_ERR_UNSUPPORTED;
+    const long long fin = in_place ? std::max<long long>(g, h_need[g]) : g;
+    if (use_ring && fin - g >= kWinRing) return GRAPHIC_ERR_UNSUPPORTED;
+    write_after[(size_t)fin].push_back((int)g);
+  }
+  auto psf_rows = [&](long long g) -> float* {
+    return psf ? psf + g * kWinRows * npix : ring + (g % kWinRing) * kWinRows * npix;
+  };
+  Timer t(ctx, st, "median");
+  hipError_t e = hipSuccess;
+  if (h_flags & 1) e = launch_median(stack, T, npix, psf_all, nullptr, median_variant(ctx, T), st);
+  for (long long g = 0; g < groups && e == hipSuccess; ++g) {
+    const long long f0 = g * kWinRows;
+    const int rows = (int)std::min<long long>(kWinRows, T - f0);
+    e = launch_median_window_rows(stack, npix, list + g * kWinKeys, h_count[g], rows, sel + f0 * 64, psf_all,
+                                  psf_rows(g), st);
+    if (!resid) continue;
+    for (int d : write_after[(size_t)g]) {
+      if (e != hipSuccess) break;
+      const long long d0 = (long long)d * kWinRows;
+      const long long n = std::min<long long>(kWinRows, T - d0) * npix;
+      e = launch_window_resid(stack + d0 * npix, psf_rows(d), resid + d0 * npix, n, st);
+    }
+  }
+  t.done();
+  return hip_ok(e);
+}
+
+// Selection, then the per-frame medians (Sect. 3.3); ws holds the selection
+// rows and counts (window_layout).
 graphic_status do_median_window(graphic_ctx ctx, long long T, int N, const float* stack, const double* times,
                                 const double* parang, double t_max, double alpha_min, float* psf, float* resid,
-                                char* sel_ws, hipStream_t st) {
-  auto* sel = reinterpret_cast<unsigned long long*>(sel_ws);
-  auto* counts = reinterpret_cast<int*>(sel_ws + align_up((size_t)T * 64 * sizeof(unsigned long long)));
+                                char* ws, hipStream_t st) {
+  if (T > kWinKeys)
+    return do_median_window_groups(ctx, T, N, stack, times, parang, t_max, alpha_min, psf, resid, ws, st);
+  const WindowLayout L = window_layout(T, (long long)N * N);
+  auto* sel = reinterpret_cast<unsigned long long*>(ws + L.sel);
+  auto* counts = reinterpret_cast<int*>(ws + L.counts);
   Timer t(ctx, st, "median");
   hipError_t e = launch_select_frames(times, parang, T, t_max, alpha_min, sel, counts, st);
   if (e == hipSuccess) e = launch_median_window(stack, T, (long long)N * N, sel, psf, resid, st);
@@ -1185,7 +1293,7 @@ graphic_status graphic_median_window(graphic_ctx ctx, const graphic_geom* geom, 
   if (psf_cube && (overlap_bad(stack, psf_cube, cube_b) || psf_cube == stack)) return GRAPHIC_ERR_ARG;
   if (resid && overlap_bad(stack, resid, cube_b)) return GRAPHIC_ERR_ARG;
   if (psf_cube && resid && (overlap_bad(psf_cube, resid, cube_b) || psf_cube == resid)) return GRAPHIC_ERR_ARG;
-  if (!ws_ok(ws, ws_bytes, window_sel_bytes(T))) return GRAPHIC_ERR_WORKSPACE;
+  if (!ws_ok(ws, ws_bytes, window_ws_bytes(T, (long long)N * N))) return GRAPHIC_ERR_WORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;
   if ((geom->flags & GRAPHIC_CHECK_FINITE) &&
       (s = check_finite(ctx, static_cast<hipStream_t>(stream), {{stack, (size_t)T * N * N}},
@@ -1227,7 +1335,7 @@ graphic_status graphic_adi_reduce_window(graphic_ctx ctx, const graphic_geom* ge
   if (residuals && (inside(residuals, cube_b) || overlap_bad(residuals, final_img, img_b))) return GRAPHIC_ERR_ARG;
   if (psf_cube && residuals && overlap_bad(psf_cube, residuals, cube_b)) return GRAPHIC_ERR_ARG;
   const size_t stack_b = residuals ? 0 : align_up(cube_b);
-  const size_t fixed = stack_b + window_sel_bytes(T);
+  const size_t fixed = stack_b + window_ws_bytes(T, (long long)N * N);
   const RotLayout L = rot_layout(T, N, P, ctx->chunk_bytes, 0);
   if (!ws_ok(ws, ws_bytes, fixed + L.params + align_up((size_t)N * P * sizeof(float)))) return GRAPHIC_ERR_WORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return GRAPHIC_ERR_HIP;

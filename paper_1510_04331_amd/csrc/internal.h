@@ -141,6 +141,27 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
                                 float* psf, float* resid, hipStream_t s);
 
+// Longer sequences run in groups of kWinRows consecutive rows; a group may
+// select at most kWinKeys distinct frames.
+constexpr int kWinRows = 256;
+constexpr int kWinKeys = 2048;
+// Per group g (one block each): the frames that any row of g selects, in
+// frame order, list[g][0..counts[g]) (counts[g] may exceed kWinKeys: then
+// only the count is meaningful); need[f / kWinRows] = the last group that
+// selects frame f (-1 if none); sel[f] = the selection of row f as bits over
+// its group's list (bit i of word j: entry j + 64 i); flags bit 0 set when a
+// row selects nothing.
+hipError_t launch_window_plan(const double* times, const double* parang, long long T, double t_max,
+                              double alpha_min, int* list, int* counts, int* need, unsigned long long* sel,
+                              int* flags, hipStream_t s);
+// Per-frame medians of one group: n_rows rows of sel over the n_keys frames
+// of list -> psf[0..n_rows) ([n_rows][npix]); an empty row takes psf_all.
+hipError_t launch_median_window_rows(const float* stack, long long npix, const int* list, int n_keys, int n_rows,
+                                     const unsigned long long* sel, const float* psf_all, float* psf,
+                                     hipStream_t s);
+// resid[i] = stack[i] - psf[i] for i < n (resid may be stack).
+hipError_t launch_window_resid(const float* stack, const float* psf, float* resid, long long n, hipStream_t s);
+
 // Registration (Sect. 3.1).  Per frame, out[f * kRegisterOut + k]: centroid x,
 // y, fitted x0, y0, I0, alpha, beta, Bg, final half sum of squared
 // residuals, Moffat FWHM, recentring shift dx = N/2 - x0, dy = N/2 - y0;

@@ -440,10 +440,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int VPT, int PB>
+//
+// Long sequences run in row groups (CH): the block then holds the n_keys
+// frames list[0..n_keys) that the group's rows select, sel rows index that
+// list (bit i of word g: list entry g + 64 i), the n_rows per-frame medians go
+// to psf[0..n_rows) and resid is unused; a row that selects nothing takes
+// psf_all, the median of every frame.
+template <int VPT, int PB, bool CH>
 __global__ void __launch_bounds__(PB * 64)
-median_window_kernel(const float* __restrict__ stack, long long T, long long npix,
-                     const unsigned long long* __restrict__ sel, float* __restrict__ psf, float* resid) {
+median_window_kernel(const float* __restrict__ stack, long long npix, const int* __restrict__ list, int n_keys,
+                     int n_rows, const unsigned long long* __restrict__ sel, const float* __restrict__ psf_all,
+                     float* __restrict__ psf, float* resid) {
   constexpr int TP = 64 * VPT;                          // padded frame count of one pixel
   constexpr int kWords = TP / 32;                       // bitmap words of one pixel
   static_assert(VPT >= 1 && VPT <= 32 && (VPT & (VPT - 1)) == 0, "VPT: power of two up to 32");
@@ -452,7 +459,7 @@ median_window_kernel(const float* __restrict__ stack, long long T, long long npi
   unsigned short* s_pos = reinterpret_cast<unsigned short*>(s_key + PB * TP);    // [PB][TP]
   unsigned* s_bits = reinterpret_cast<unsigned*>(s_pos + PB * TP);              // [PB][kWords]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int Ti = (int)T;
+  const int Ti = n_rows;
   const unsigned nb = gridDim.x, b = blockIdx.x;
   const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
   const long long pix0 = (long long)tile * PB;
@@ -465,7 +472,9 @@ median_window_kernel(const float* __restrict__ stack, long long T, long long npi
 #pragma unroll 4
     for (int i = 0; i < VPT; ++i) {
       const int f = g + 64 * i;
-      s_key[px * TP + f] = (ok && f < Ti) ? key_of(stack[(long long)f * npix + pix0 + px]) : 0xFFFFFFFFu;
+      const bool in = ok && f < n_keys;
+      const long long fr = CH ? (in ? list[f] : 0) : f;
+      s_key[px * TP + f] = in ? key_of(stack[fr * npix + pix0 + px]) : 0xFFFFFFFFu;
     }
   }
   __syncthreads();
@@ -546,13 +555,20 @@ median_window_kernel(const float* __restrict__ stack, long long T, long long npi
       const int at = b0 + nth_set_bit(m, k - (incl - cnt));
       return key[__builtin_amdgcn_readlane(at, L)];
     };
-    const unsigned klo = K == 0u ? 0u : (K - 1u) / 2u;
-    const float lo = val_of(key_of_rank(klo));
-    const float hi = K / 2u == klo ? lo : val_of(key_of_rank(K / 2u));
-    const float med = (lo + hi) * 0.5f;
+    float med;
+    if (CH && K == 0u) {                                // K is wave-uniform
+      med = pix_ok ? psf_all[pix] : 0.0f;
+    } else {
+      const unsigned klo = K == 0u ? 0u : (K - 1u) / 2u;
+      const float lo = val_of(key_of_rank(klo));
+      const float hi = K / 2u == klo ? lo : val_of(key_of_rank(K / 2u));
+      med = (lo + hi) * 0.5f;
+    }
     if (lane == 0 && pix_ok) {
       if (psf != nullptr) psf[(size_t)f * npix + pix] = med;
-      if (resid != nullptr) resid[(size_t)f * npix + pix] = val_of(key[pos[f]]) - med;
+      if constexpr (!CH) {
+        if (resid != nullptr) resid[(size_t)f * npix + pix] = val_of(key[pos[f]]) - med;
+      }
     }
     cur = nxt;
     wave_sync();
@@ -610,6 +626,99 @@ __global__ void __launch_bounds__(64) select_frames_kernel(const double* __restr
   }
   sel[f * 64 + g] = bits;
   if (g == 0) counts[f] = c;
+}
+
+// Row groups of a long sequence.  Block g takes rows g kWinRows ... (one
+// block of four waves per group).  The union pass tests every frame k against
+// the group's rows with the selection's own comparisons and compacts the
+// selected frames in frame order (a wave ballot per 256 frames); the rows pass
+// then re-tests each row against the union only.  The union pass costs T x
+// kWinRows comparisons per group, which bounds the sequences this serves to a
+// few hundred thousand frames.
+constexpr int kPlanThreads = 256;
+
+__global__ void __launch_bounds__(256) window_plan_init_kernel(int* __restrict__ need, long long n_groups,
+                                                               int* __restrict__ flags) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n_groups) need[i] = -1;
+  if (i == 0) *flags = 0;
+}
+
+__global__ void __launch_bounds__(kPlanThreads) window_plan_kernel(const double* __restrict__ times,
+                                                                   const double* __restrict__ parang, long long T,
+                                                                   double t_max, double alpha_min,
+                                                                   int* __restrict__ list, int* __restrict__ counts,
+                                                                   int* __restrict__ need,
+                                                                   unsigned long long* __restrict__ sel,
+                                                                   int* __restrict__ flags) {
+  constexpr int kWaves = kPlanThreads / 64;
+  __shared__ double s_t[kWinRows], s_a[kWinRows];       // the group's rows
+  __shared__ double s_lt[kWinKeys], s_la[kWinKeys];     // the union's frames
+  __shared__ int s_wc[kWaves];
+  __shared__ int s_n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long long grp = blockIdx.x, f0 = grp * kWinRows;
+  const int nr = (int)(T - f0 < kWinRows ? T - f0 : kWinRows);
+  if (tid < nr) {
+    s_t[tid] = times[f0 + tid];
+    s_a[tid] = parang[f0 + tid];
+  }
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  int* glist = list + grp * kWinKeys;
+  for (long long k0 = 0; k0 < T; k0 += kPlanThreads) {
+    const long long k = k0 + tid;
+    double tk = 0.0, ak = 0.0;
+    bool in = false;
+    if (k < T) {
+      tk = times[k];
+      ak = parang[k];
+      for (int r = 0; r < nr && !in; ++r) in = fabs(tk - s_t[r]) < t_max && fabs(ak - s_a[r]) > alpha_min;
+    }
+    const unsigned long long b = __ballot(in);
+    if (lane == 0) s_wc[w] = __popcll(b);
+    __syncthreads();
+    int at = s_n + __popcll(b & ((1ull << lane) - 1ull));
+    for (int i = 0; i < w; ++i) at += s_wc[i];
+    if (in) {
+      if (at < kWinKeys) {
+        glist[at] = (int)k;
+        s_lt[at] = tk;
+        s_la[at] = ak;
+      }
+      atomicMax(&need[k / kWinRows], (int)grp);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int add = 0;
+      for (int i = 0; i < kWaves; ++i) add += s_wc[i];
+      s_n += add;
+    }
+    __syncthreads();
+  }
+  const int n = s_n;
+  if (tid == 0) counts[grp] = n;
+  if (n > kWinKeys) return;                              // rejected on the host
+  // each wave builds rows w, w + kWaves, ...; lane j owns word j of a row
+  for (int r = w; r < nr; r += kWaves) {
+    const double tf = s_t[r], af = s_a[r];
+    unsigned long long bits = 0ull;
+    for (int i = 0; i < kWinKeys / 64; ++i) {
+      const int e = lane + 64 * i;
+      if (e >= n) break;
+      if (fabs(s_lt[e] - tf) < t_max && fabs(s_la[e] - af) > alpha_min) bits |= 1ull << i;
+    }
+    sel[(f0 + r) * 64 + lane] = bits;
+    if (__ballot(bits != 0ull) == 0ull && lane == 0) atomicOr(flags, 1);
+  }
+}
+
+// resid = stack - psf, elementwise (in place allowed: each thread rewrites
+// what it reads).
+__global__ void __launch_bounds__(256) window_resid_kernel(const float* stack, const float* __restrict__ psf,
+                                                           float* resid, long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    resid[i] = stack[i] - psf[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -772,30 +881,73 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
   return hipGetLastError();
 }
 
-template <int V, int PB>
-static hipError_t launch_window_v(const float* stack, long long T, long long npix, const unsigned long long* sel,
-                                  float* psf, float* resid, hipStream_t s) {
+template <int V, int PB, bool CH>
+static hipError_t launch_window_v(const float* stack, long long npix, const int* list, int n_keys, int n_rows,
+                                  const unsigned long long* sel, const float* psf_all, float* psf, float* resid,
+                                  hipStream_t s) {
   constexpr int TP = 64 * V;
   const size_t lds = (size_t)PB * TP * (sizeof(unsigned) + sizeof(unsigned short)) + (size_t)PB * (TP / 32) * 4;
   const unsigned blocks = (unsigned)((npix + PB - 1) / PB);
-  if (hipError_t e = set_dynamic_lds(median_window_kernel<V, PB>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((median_window_kernel<V, PB>), dim3(blocks), dim3(PB * 64), lds, s, stack, T, npix, sel, psf,
-                     resid);
+  if (hipError_t e = set_dynamic_lds(median_window_kernel<V, PB, CH>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((median_window_kernel<V, PB, CH>), dim3(blocks), dim3(PB * 64), lds, s, stack, npix, list,
+                     n_keys, n_rows, sel, psf_all, psf, resid);
   return hipGetLastError();
 }
 
+// Keys per lane from the frames one block holds; pixels per block: at most
+// about 50 KB of LDS, so that three blocks share a compute unit and their
+// frame loops hide each other's latency.
+template <bool CH>
+static hipError_t launch_window_any(const float* stack, long long npix, const int* list, int n_keys, int n_rows,
+                                    const unsigned long long* sel, const float* psf_all, float* psf, float* resid,
+                                    hipStream_t s) {
+  const int vpt = (n_keys + kGroups - 1) / kGroups;
+#define GRAPHIC_WINDOW_CASE(V, PB)                                                                          \
+  if (vpt <= V)                                                                                            \
+    return launch_window_v<V, PB, CH>(stack, npix, list, n_keys, n_rows, sel, psf_all, psf, resid, s);
+  GRAPHIC_WINDOW_CASE(1, 16)
+  GRAPHIC_WINDOW_CASE(2, 16)
+  GRAPHIC_WINDOW_CASE(4, 16)
+  GRAPHIC_WINDOW_CASE(8, 16)
+  GRAPHIC_WINDOW_CASE(16, 8)
+  GRAPHIC_WINDOW_CASE(32, 4)
+#undef GRAPHIC_WINDOW_CASE
+  return hipErrorInvalidValue;   // more than 2048 keys: rejected on the host before launch
+}
+
 hipError_t launch_median_window(const float* stack, long long T, long long npix, const unsigned long long* sel,
-                                float* psf, float* resid, hipStream_t s) {  if (T <= 0 || npix <= 0) return hipSuccess;
-  const long long vpt = (T + kGroups - 1) / kGroups;
-  // pixels per block: at most about 50 KB of LDS, so that three blocks share
-  // a compute unit and their frame loops hide each other's latency
-  if (vpt <= 1) return launch_window_v<1, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 2) return launch_window_v<2, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 4) return launch_window_v<4, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 8) return launch_window_v<8, 16>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 16) return launch_window_v<16, 8>(stack, T, npix, sel, psf, resid, s);
-  if (vpt <= 32) return launch_window_v<32, 4>(stack, T, npix, sel, psf, resid, s);
-  return hipErrorInvalidValue;   // T > 2048: rejected on the host before launch
+                                float* psf, float* resid, hipStream_t s) {
+  if (T <= 0 || npix <= 0) return hipSuccess;
+  if (T > kWinKeys) return hipErrorInvalidValue;
+  return launch_window_any<false>(stack, npix, nullptr, (int)T, (int)T, sel, nullptr, psf, resid, s);
+}
+
+hipError_t launch_window_plan(const double* times, const double* parang, long long T, double t_max,
+                              double alpha_min, int* list, int* counts, int* need, unsigned long long* sel,
+                              int* flags, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  const long long groups = (T + kWinRows - 1) / kWinRows;
+  hipLaunchKernelGGL(window_plan_init_kernel, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, need, groups,
+                     flags);
+  hipLaunchKernelGGL(window_plan_kernel, dim3((unsigned)groups), dim3(kPlanThreads), 0, s, times, parang, T, t_max,
+                     alpha_min, list, counts, need, sel, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_median_window_rows(const float* stack, long long npix, const int* list, int n_keys, int n_rows,
+                                     const unsigned long long* sel, const float* psf_all, float* psf,
+                                     hipStream_t s) {
+  if (n_rows <= 0 || npix <= 0) return hipSuccess;
+  if (n_keys < 0 || n_keys > kWinKeys || n_rows > kWinRows) return hipErrorInvalidValue;
+  return launch_window_any<true>(stack, npix, list, n_keys, n_rows, sel, psf_all, psf, nullptr, s);
+}
+
+hipError_t launch_window_resid(const float* stack, const float* psf, float* resid, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long want = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(window_resid_kernel, dim3(blocks), dim3(256), 0, s, stack, psf, resid, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_median_nan(const float* stack, long long T, long long npix, float* out, hipStream_t s) {

@@ -96,8 +96,21 @@ def test_window_workspace_sizes(lib):
     assert sz.value >= 100 * 64 * 8 + 100 * 4
     assert lib.graphic_workspace_size(None, _abi.OP_ADI_WINDOW, ctypes.byref(g), ctypes.byref(sz)) == _abi.OK
     assert sz.value >= 100 * 64 * 64 * 4 + 100 * 64 * 8 + 64 * 128 * 4
-    big = _abi.Geom(2049, 64, 0, 0)       # the per-frame PSF holds up to 2048 frames
+    # longer sequences run in groups of 256 rows: the plan (2048 frame indices
+    # and two ints per group, a flag word), one image for the rows that select
+    # nothing and a ring of 9 x 256 PSF frames
+    small = ctypes.c_size_t()
+    lib.graphic_workspace_size(None, _abi.OP_MEDIAN_WINDOW, ctypes.byref(_abi.Geom(2048, 64, 0, 0)),
+                               ctypes.byref(small))
+    long_ = _abi.Geom(2049, 64, 0, 0)
+    assert lib.graphic_workspace_size(None, _abi.OP_MEDIAN_WINDOW, ctypes.byref(long_), ctypes.byref(sz)) == _abi.OK
+    groups = 9
+    assert sz.value >= small.value + groups * 2048 * 4 + 64 * 64 * 4 + 9 * 256 * 64 * 64 * 4
+    assert sz.value <= small.value + groups * 2048 * 4 + 64 * 64 * 4 + 9 * 256 * 64 * 64 * 4 + 16 * 256
+    top = _abi.Geom(1 << 18, 64, 0, 0)
+    big = _abi.Geom((1 << 18) + 1, 64, 0, 0)    # the plan compares all pairs of frames
     for op in (_abi.OP_MEDIAN_WINDOW, _abi.OP_ADI_WINDOW):
+        assert lib.graphic_workspace_size(None, op, ctypes.byref(top), ctypes.byref(sz)) == _abi.OK
         assert lib.graphic_workspace_size(None, op, ctypes.byref(big), ctypes.byref(sz)) == _abi.ERR_UNSUPPORTED
 
 

@@ -1,0 +1,149 @@
+"""GPU: the per-frame PSF of Sect. 3.3 on sequences longer than 2048 frames.
+
+Such sequences run in groups of 256 consecutive frames; each group sorts only
+the frames its rows select.  The bar is the one of the short sequences: the
+per-frame medians bit-exact against the oracle's float32 medians of the
+oracle's own selection, residuals the float32 differences, in every output
+mode (PSF and residuals apart, residuals over the stack with and without a
+PSF cube, PSF alone).  The cases cover rows that select nothing (they take
+the median of all frames, through the streaming select past 4096 frames),
+groups that select up to 2048 frames, a frame selected by a row far later
+(the residuals then wait for that row), and the selections the library
+rejects before writing anything."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1510_04331_amd  # noqa: F401
+    return torch, torch.device("cuda:0")
+
+
+def _stack(T, N, seed):
+    rng = np.random.default_rng(seed)
+    st = (rng.normal(size=(T, N, N)) * 4 + 30).astype(np.float32)
+    st[:, 0, 0] = np.round(st[:, 0, 0])                  # ties
+    st[:, 0, 1] = 0.0
+    st[::2, 0, 1] = -0.0                                 # signed zeros
+    st[:, 1, 1] = 7.0                                    # all equal
+    return st
+
+
+def _sequence(T, seed):
+    """Frames about 2 s apart; the field turns slowly for the first 200
+    frames (so that early frames select nothing and fall back), then steadily,
+    and turns back over the last 300."""
+    rng = np.random.default_rng(seed)
+    t = 2.0 * np.arange(T) + rng.uniform(0.0, 0.5, T)
+    i = np.arange(T, dtype=np.float64)
+    a = np.where(i < 200, 0.001 * i, 0.2 + 0.05 * (i - 200))
+    turn = T - 300
+    a = np.where(i > turn, a[turn] - 0.03 * (i - turn), a)
+    return t, a
+
+
+def _check_all_modes(G, torch, dev, st, t, a, t_max, amin):
+    sel = O.select_frames(t, a, t_max, amin)
+    ref = O.median_window_f32(st, sel)
+    want_res = (st - ref).astype(np.float32).tobytes()
+    x = torch.from_numpy(st).to(dev)
+    psf, res = G.median_window(x, t, a, t_max, amin, psf=True, resid=True)
+    assert psf.cpu().numpy().tobytes() == ref.tobytes()
+    assert res.cpu().numpy().tobytes() == want_res
+    only = G.median_window(x, t, a, t_max, amin, psf=True)
+    assert only.cpu().numpy().tobytes() == ref.tobytes()
+    y = x.clone()
+    G.median_window(y, t, a, t_max, amin, psf=False, inplace=True)      # PSF held in the ring
+    assert y.cpu().numpy().tobytes() == want_res
+    y = x.clone()
+    p2, _ = G.median_window(y, t, a, t_max, amin, psf=True, inplace=True)
+    assert p2.cpu().numpy().tobytes() == ref.tobytes()
+    assert y.cpu().numpy().tobytes() == want_res
+    return sel
+
+
+@pytest.mark.parametrize("T,N,t_max", [(2049, 6, 150.0), (2500, 6, 150.0), (2500, 8, 1400.0), (4100, 6, 150.0)])
+def test_long_window_bit_exact(torch_dev, T, N, t_max):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("long window T=%d N=%d t_max=%g" % (T, N, t_max), flush=True)
+    st = _stack(T, N, T + N)
+    t, a = _sequence(T, T)
+    sel = _check_all_modes(G, torch, dev, st, t, a, t_max, 2.0)
+    n_sel = sel.sum(axis=1)
+    assert (n_sel < T).any()                              # real selections
+    if t_max < 1000.0:
+        assert (n_sel == T).any()                         # and rows that fall back to all frames
+
+
+def test_long_window_far_reader(torch_dev):
+    """Frame 0 carries the time of frame 2400, so rows near 2400 select it:
+    written over the stack, frame 0's residual waits for them (with a PSF
+    cube); without one the library declines, as its ring holds nine groups."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    T, N = 2500, 6
+    st = _stack(T, N, 11)
+    t, a = _sequence(T, 11)
+    t[0] = t[2400]
+    a[0] = a[2400] + 10.0
+    sel = O.select_frames(t, a, 150.0, 2.0)
+    assert sel[2400, 0] and sel[2450, 0]
+    ref = O.median_window_f32(st, sel)
+    x = torch.from_numpy(st).to(dev)
+    psf, _ = G.median_window(x, t, a, 150.0, 2.0, psf=True, inplace=True)
+    assert psf.cpu().numpy().tobytes() == ref.tobytes()
+    assert x.cpu().numpy().tobytes() == (st - ref).astype(np.float32).tobytes()
+    y = torch.from_numpy(st).to(dev)
+    with pytest.raises(G.GraphicError) as e:
+        G.median_window(y, t, a, 150.0, 2.0, psf=False, inplace=True)
+    assert "UNSUPPORTED" in str(e.value)
+    assert y.cpu().numpy().tobytes() == st.tobytes()     # nothing written
+
+
+def test_long_window_rejects_wide_groups(torch_dev):
+    """Shuffled times: each group's rows select frames from the whole
+    sequence, more than 2048 of them, and nothing is written."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    T, N = 3000, 6
+    st = _stack(T, N, 5)
+    t, a = _sequence(T, 5)
+    t = np.random.default_rng(6).permutation(t)
+    x = torch.from_numpy(st).to(dev)
+    with pytest.raises(G.GraphicError) as e:
+        G.median_window(x, t, a, 150.0, 2.0, psf=False, inplace=True)
+    assert "UNSUPPORTED" in str(e.value)
+    assert x.cpu().numpy().tobytes() == st.tobytes()
+
+
+def test_long_adi_window_against_oracle(torch_dev):
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    print("long adi window 2300 x 16^2", flush=True)
+    T, N = 2300, 16
+    rng = np.random.default_rng(21)
+    yy, xx = np.mgrid[0:N, 0:N]
+    star = 1e3 * np.exp(-((xx - 8.0) ** 2 + (yy - 8.0) ** 2) / (2 * 1.7 ** 2))
+    cube = (star[None] + rng.normal(0.0, 5.0, (T, N, N))).astype(np.float32)
+    dx, dy = rng.uniform(-0.5, 0.5, T), rng.uniform(-0.5, 0.5, T)
+    t, pa = _sequence(T, 21)
+    fin, psf = G.adi_reduce_window(torch.from_numpy(cube).to(dev), dx, dy, pa, t, 150.0, 2.0, psf=True)
+    ref = O.adi_reduce_window(cube, dx, dy, pa, t, 150.0, 2.0)
+    scale = np.linalg.norm(ref["psf"][T // 2])
+    got = psf.cpu().numpy()
+    for i in (0, 100, 1000, 2047, 2048, 2299):
+        assert np.linalg.norm(got[i] - ref["psf"][i]) / scale <= 1e-5, i
+    assert np.linalg.norm(fin.cpu().numpy() - ref["final"]) / scale <= 1e-5
+    # without a PSF cube the PSF waits in the ring: the same result, bit for bit
+    fin2 = G.adi_reduce_window(torch.from_numpy(cube).to(dev), dx, dy, pa, t, 150.0, 2.0)
+    assert fin2.cpu().numpy().tobytes() == fin.cpu().numpy().tobytes()
