@@ -575,6 +575,189 @@ median_window_kernel(const float* __restrict__ stack, long long npix, const int*
   }
 }
 
+// The same per-frame medians with Q pixels per wave, 64 / Q lanes each.  The
+// selection is a property of the frame, not of the pixel, so all Q pixels see
+// the same count K and the same ranks: one pass over the changed selection
+// bits, one loop and one segmented scan serve Q pixels.  Each lane covers
+// Q VPT bitmap bits.  Rank (K - 1) / 2 takes the bit search; rank K / 2, when
+// it differs, is the next marked bit after it in the same lane or the lowest
+// marked bit of the next lane that has one.  The launcher uses Q = 2: with
+// Q = 4 the LDS-bound residency leaves too few waves to hide the loop's LDS
+// latency (54 against 40 ms at 1024 x 512^2).
+// Inclusive prefix sums over each group of 64 / Q lanes of the wave (Q = 4:
+// rows of 16; Q = 2: the row_bcast:15 step joins rows 0-1 and 2-3).
+template <int Q>
+__device__ __forceinline__ unsigned seg_incl_scan(unsigned x) {
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  if constexpr (Q == 2)
+    x += (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  return x;
+}
+
+// Index of the j-th set bit (from 0) of a 64-bit m (j < popcount(m)).
+__device__ __forceinline__ int nth_set_bit64(unsigned long long m, unsigned j) {
+  const unsigned lo = (unsigned)m, lowc = (unsigned)__popc(lo);
+  return j < lowc ? nth_set_bit(lo, j) : 32 + nth_set_bit((unsigned)(m >> 32), j - lowc);
+}
+
+template <int VPT, int PB, bool CH, int Q>
+__global__ void __launch_bounds__(PB * 64 / Q)
+median_window_q_kernel(const float* __restrict__ stack, long long npix, const int* __restrict__ list,
+                       int n_keys, int n_rows, const unsigned long long* __restrict__ sel,
+                       const float* __restrict__ psf_all, float* __restrict__ psf, float* resid) {
+  constexpr int TP = 64 * VPT;                          // padded frame count of one pixel
+  constexpr int kWords = TP / 32;                       // bitmap words of one pixel
+  constexpr int LP = 64 / Q;                            // lanes per pixel
+  constexpr int BQ = Q * VPT;                           // bitmap bits per lane
+  static_assert(VPT >= 1 && VPT <= 32 && (VPT & (VPT - 1)) == 0, "VPT: power of two up to 32");
+  static_assert((Q == 2 || Q == 4) && PB % Q == 0 && BQ <= 64, "Q pixels per wave, at most 64 bits per lane");
+  extern __shared__ unsigned s_dyn[];
+  unsigned* s_key = s_dyn;                                                       // [PB][TP]
+  unsigned short* s_pos = reinterpret_cast<unsigned short*>(s_key + PB * TP);    // [PB][TP]
+  unsigned* s_bits = reinterpret_cast<unsigned*>(s_pos + PB * TP);              // [PB][kWords]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int Ti = n_rows;
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned tile = (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+  const long long pix0 = (long long)tile * PB;
+
+  // 1. the tile's stack into LDS, coalesced over the pixels
+  for (int idx = tid; idx < PB * TP; idx += PB * LP) {
+    const int px = idx % PB, f = idx / PB;
+    const bool in = pix0 + px < npix && f < n_keys;
+    const long long fr = CH ? (in ? list[f] : 0) : f;
+    s_key[px * TP + f] = in ? key_of(stack[fr * npix + pix0 + px]) : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+
+  // 2. wave w sorts pixels Q w ... Q w + Q - 1, one after the other
+  for (int q = 0; q < Q; ++q) {
+    unsigned* key = s_key + (Q * w + q) * TP;
+    unsigned short* pos = s_pos + (Q * w + q) * TP;
+    unsigned long long v[VPT];
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+      const int e = lane * VPT + r;
+      v[r] = ((unsigned long long)key[e] << 11) | (unsigned)e;
+    }
+#pragma unroll
+    for (int k = 2; k <= TP; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= VPT) {
+          const bool upper = (lane & (j / VPT)) != 0;
+          const bool asc = ((lane * VPT) & k) == 0;
+#pragma unroll
+          for (int r = 0; r < VPT; ++r) {
+            const unsigned long long o = shfl_xor_u64(v[r], j / VPT);
+            v[r] = (asc != upper) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < VPT; ++r) {
+            if ((r & j) != 0) continue;
+            const bool asc = (((lane * VPT + r) & k) == 0);
+            const unsigned long long x = v[r], y = v[r | j];
+            const unsigned long long lo = x < y ? x : y, hi = x < y ? y : x;
+            v[r] = asc ? lo : hi;
+            v[r | j] = asc ? hi : lo;
+          }
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < VPT; ++r) {
+      const int e = lane * VPT + r;
+      key[e] = (unsigned)(v[r] >> 11);
+      pos[(int)(v[r] & 0x7FFu)] = (unsigned short)e;
+    }
+  }
+  for (int i = lane; i < Q * kWords; i += 64) s_bits[Q * w * kWords + i] = 0u;
+  wave_sync();
+
+  // 3. frame loop: lanes h LP ... h LP + LP - 1 serve pixel Q w + h
+  const int h = lane / LP, hl = lane % LP;
+  const unsigned short* wpos = s_pos + Q * w * TP;
+  unsigned* wbits = s_bits + Q * w * kWords;
+  const unsigned* key = s_key + (Q * w + h) * TP;
+  const unsigned short* pos = wpos + h * TP;
+  const unsigned* bits = wbits + h * kWords;
+  const long long pix = pix0 + Q * w + h;
+  const bool pix_ok = pix < npix;
+  const int b0 = hl * BQ;
+  unsigned long long prev = 0ull;
+  unsigned long long cur = sel[lane];
+#pragma unroll 1
+  for (int f = 0; f < Ti; ++f) {
+    const unsigned long long nxt = f + 1 < Ti ? sel[(size_t)(f + 1) * kGroups + lane] : 0ull;
+    unsigned long long d = cur ^ prev;
+    prev = cur;
+    while (d != 0ull) {
+      const int i = __ffsll((long long)d) - 1;
+      d &= d - 1ull;
+      int p[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) p[q] = wpos[q * TP + lane + 64 * i];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) atomicXor(&wbits[q * kWords + (p[q] >> 5)], 1u << (p[q] & 31));
+    }
+    wave_sync();
+    unsigned long long m;
+    if constexpr (BQ == 64) {
+      m = *reinterpret_cast<const unsigned long long*>(bits + (b0 >> 5));
+    } else {
+      const unsigned word = bits[b0 >> 5];
+      m = BQ == 32 ? word : (word >> (b0 & 31)) & ((1u << (BQ & 31)) - 1u);
+    }
+    const unsigned cnt = (unsigned)__popcll(m);
+    const unsigned incl = seg_incl_scan<Q>(cnt);
+    const unsigned K = (unsigned)__builtin_amdgcn_readlane((int)incl, LP - 1);   // the same in every group
+    // position held by the first lane of each group with incl > k, from v
+    auto pick = [&](unsigned k, int v) -> int {
+      const unsigned long long bal = __ballot(incl > k);
+      int a = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const unsigned seg = (unsigned)(bal >> (q * LP)) & (unsigned)((1ull << LP) - 1ull);
+        const int aq = __builtin_amdgcn_readlane(v, q * LP + __ffs((int)seg) - 1);
+        a = h == q ? aq : a;
+      }
+      return a;
+    };
+    float med;
+    if (CH && K == 0u) {                                // K is wave-uniform
+      med = pix_ok ? psf_all[pix] : 0.0f;
+    } else {
+      const unsigned klo = K == 0u ? 0u : (K - 1u) / 2u;
+      const unsigned before = incl - cnt;               // selected positions ahead of this lane's stretch
+      const int r_lo = nth_set_bit64(m, klo - before);
+      const float lo = val_of(key[pick(klo, b0 + r_lo)]);
+      float hi = lo;
+      if (K / 2u != klo) {
+        // rank klo + 1: the next marked bit after rank klo's in the same
+        // lane, else the lowest marked bit of the next lane that has one
+        const bool holds_lo = klo >= before && klo < incl;
+        const unsigned long long above = m & ~((2ull << r_lo) - 1ull);
+        const int r_hi = holds_lo ? __ffsll((long long)above) - 1 : __ffsll((long long)m) - 1;
+        hi = val_of(key[pick(klo + 1u, b0 + r_hi)]);
+      }
+      med = (lo + hi) * 0.5f;
+    }
+    if (hl == 0 && pix_ok) {
+      if (psf != nullptr) psf[(size_t)f * npix + pix] = med;
+      if constexpr (!CH) {
+        if (resid != nullptr) resid[(size_t)f * npix + pix] = val_of(key[pos[f]]) - med;
+      }
+    }
+    cur = nxt;
+    wave_sync();
+  }
+}
+
 // Per-pixel median ignoring NaN values (the master sky of Sect. 3.2.1: star
 // regions are NaN); a pixel with no value left is NaN.
 template <int VPT, bool BUF>
@@ -881,6 +1064,10 @@ hipError_t launch_select_frames(const double* times, const double* parang, long 
   return hipGetLastError();
 }
 
+// Up to 1024 keys per pixel two pixels share a wave (1.2x at 1024 frames,
+// 1.9x at 256); at 2048 the one-pixel form keeps twice the waves that its
+// LDS allows per compute unit and is faster (134 against 164 ms at 2048 x
+// 512^2).
 template <int V, int PB, bool CH>
 static hipError_t launch_window_v(const float* stack, long long npix, const int* list, int n_keys, int n_rows,
                                   const unsigned long long* sel, const float* psf_all, float* psf, float* resid,
@@ -888,9 +1075,15 @@ static hipError_t launch_window_v(const float* stack, long long npix, const int*
   constexpr int TP = 64 * V;
   const size_t lds = (size_t)PB * TP * (sizeof(unsigned) + sizeof(unsigned short)) + (size_t)PB * (TP / 32) * 4;
   const unsigned blocks = (unsigned)((npix + PB - 1) / PB);
-  if (hipError_t e = set_dynamic_lds(median_window_kernel<V, PB, CH>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((median_window_kernel<V, PB, CH>), dim3(blocks), dim3(PB * 64), lds, s, stack, npix, list,
-                     n_keys, n_rows, sel, psf_all, psf, resid);
+  if constexpr (V <= 16) {
+    if (hipError_t e = set_dynamic_lds(median_window_q_kernel<V, PB, CH, 2>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((median_window_q_kernel<V, PB, CH, 2>), dim3(blocks), dim3(PB * 32), lds, s, stack, npix,
+                       list, n_keys, n_rows, sel, psf_all, psf, resid);
+  } else {
+    if (hipError_t e = set_dynamic_lds(median_window_kernel<V, PB, CH>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((median_window_kernel<V, PB, CH>), dim3(blocks), dim3(PB * 64), lds, s, stack, npix, list,
+                       n_keys, n_rows, sel, psf_all, psf, resid);
+  }
   return hipGetLastError();
 }
 
