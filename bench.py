@@ -787,6 +787,7 @@ def main():
                          "avg_launch_ms": ms / n}
     G.timing_enable(False)
     assert torch.isfinite(final).all()
+    copy_ceiling = measure_copy(torch, cube)
     verify = None
     if args.verify_frames > 0:
         rng = np.random.default_rng(synth.BASE_SEED + 11)
@@ -842,6 +843,7 @@ def main():
                                % (T, N, N, P, P),
                    "frames": T, "size": N, "pad": P, "parallelism": "single GPU"},
         "roofline": roofline(fams[dom], dom, traffic),
+        "copy_ceiling": copy_ceiling,
         "cpu_baseline": cpu,
         "tuning": tuning.strip().split("\n") if tuning else "defaults",
         "latency_ms": {"p50": round(pct(0.5), 3), "p99": round(pct(0.99), 3)},
@@ -853,6 +855,29 @@ def main():
         "per_frame_check": verify,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_copy(torch, cube, reps=3):
+    """Measured HBM ceiling beside the published peak: a plain device-to-device
+    copy of the cube (torch copy_), read + write bytes over the fastest of
+    `reps` copies, timed with events on the copy's stream, outside the timed
+    region."""
+    dst = torch.empty_like(cube)
+    dst.copy_(cube)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(cube)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del dst
+    torch.cuda.empty_cache()
+    gbs = 2.0 * cube.numel() * cube.element_size() / (best * 1e-3) / 1e9
+    return {"GBps": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_copy":
+            2 * cube.numel() * cube.element_size(), "what": "device-to-device copy of the cube, best of %d" % reps}
 
 
 if __name__ == "__main__":
