@@ -38,7 +38,7 @@ __all__ = [
     "padded_size", "pad", "crop", "signed_freq", "phasor", "shift",
     "shear_rows", "shear_cols", "flip180", "reduce_angle", "rotate",
     "median_f32", "median_f64", "adi_reduce", "dirichlet_kernel",
-    "alpha_min_deg", "select_frames", "median_window_f32", "adi_reduce_window",
+    "alpha_min_deg", "select_frames", "select_row", "median_window_f32", "adi_reduce_window",
 ]
 
 
@@ -333,6 +333,18 @@ def select_frames(times, parang_deg, t_max, alpha_min):
     empty = ~sel.any(axis=1)
     sel[empty, :] = True
     return sel
+
+
+def select_row(times, parang_deg, t_max, alpha_min, i):
+    """Row i of ``select_frames`` alone (Sect. 3.3 selection with the
+    all-frames fallback), in O(T): for sequences too long for the T x T
+    matrix."""
+    t = np.asarray(times, dtype=np.float64)
+    a = np.asarray(parang_deg, dtype=np.float64)
+    row = (np.abs(t - t[i]) < t_max) & (np.abs(a - a[i]) > alpha_min)
+    if not row.any():
+        row[:] = True
+    return row
 
 
 def median_window_f32(stack, sel):

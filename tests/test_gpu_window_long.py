@@ -147,3 +147,31 @@ def test_long_adi_window_against_oracle(torch_dev):
     # without a PSF cube the PSF waits in the ring: the same result, bit for bit
     fin2 = G.adi_reduce_window(torch.from_numpy(cube).to(dev), dx, dy, pa, t, 150.0, 2.0)
     assert fin2.cpu().numpy().tobytes() == fin.cpu().numpy().tobytes()
+
+
+def test_long_window_maximum_frames(torch_dev):
+    """The longest sequence the call takes, 2^18 frames (1024 row groups), on
+    a small frame: sampled rows checked one by one against the oracle's
+    selection criterion and float32 median, with the residuals written over
+    the stack (the ring path)."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    T, N = 1 << 18, 6
+    print("long window at the frame limit: T=%d N=%d" % (T, N), flush=True)
+    st = _stack(T, N, 99)
+    t, a = _sequence(T, 99)
+    t_max, amin = 150.0, 2.0
+    x = torch.from_numpy(st).to(dev)
+    psf = G.median_window(x, t, a, t_max, amin, psf=True, inplace=True)[0].cpu().numpy()
+    res = x.cpu().numpy()
+    rng = np.random.default_rng(5)
+    rows = sorted({0, 1, 255, 256, 2047, 2048, T // 2 - 1, T // 2, T - 257, T - 256, T - 1} |
+                  {int(r) for r in rng.integers(0, T, 12)})
+    fallback = 0
+    for f in rows:
+        sel = O.select_row(t, a, t_max, amin, f)
+        fallback += int(sel.all())
+        ref = O.median_f32(st[sel])
+        assert psf[f].tobytes() == ref.tobytes(), f
+        assert res[f].tobytes() == (st[f] - ref).astype(np.float32).tobytes(), f
+    assert 0 < fallback < len(rows)

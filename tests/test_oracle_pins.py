@@ -331,6 +331,21 @@ def test_select_frames_by_hand():
     assert sel.all()
 
 
+def test_select_row_by_hand():
+    # the same frames one row at a time
+    t = np.arange(8.0)
+    a = 2.0 * np.arange(8.0)
+    for i in range(8):
+        want = {k for k in range(8) if 2 <= abs(k - i) <= 3}
+        assert set(np.flatnonzero(O.select_row(t, a, 3.5, 3.0, i))) == want, i
+        assert O.select_row(t, np.zeros(8), 10.0, 1.0, i).all()
+    # a frame alone in time falls back while its neighbours select each other
+    t2 = np.array([0.0, 1.0, 2.0, 100.0])
+    a2 = np.array([0.0, 5.0, 10.0, 0.0])
+    assert list(O.select_row(t2, a2, 3.0, 4.0, 3)) == [True] * 4
+    assert list(O.select_row(t2, a2, 3.0, 4.0, 0)) == [False, True, True, False]
+
+
 def test_window_median_brute_force():
     rng = np.random.default_rng(12)
     st = rng.normal(size=(11, 3, 4)).astype(np.float32)
