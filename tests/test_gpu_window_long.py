@@ -110,6 +110,25 @@ def test_long_window_far_reader(torch_dev):
     assert y.cpu().numpy().tobytes() == st.tobytes()     # nothing written
 
 
+def test_long_window_reader_at_ring_limit(torch_dev):
+    """Frame 0 carries the time of frame 2200 (group 8): its residual must
+    wait eight groups, the most the ring of nine groups allows without a PSF
+    cube, so the ring's oldest slot is read just before it is reused."""
+    torch, dev = torch_dev
+    import paper_1510_04331_amd as G
+    T, N = 2500, 6
+    st = _stack(T, N, 12)
+    t, a = _sequence(T, 12)
+    t[0] = t[2200]
+    a[0] = a[2200] + 10.0
+    sel = O.select_frames(t, a, 150.0, 2.0)
+    assert sel[2200, 0] and not sel[2400:, 0].any()
+    ref = O.median_window_f32(st, sel)
+    x = torch.from_numpy(st).to(dev)
+    G.median_window(x, t, a, 150.0, 2.0, psf=False, inplace=True)
+    assert x.cpu().numpy().tobytes() == (st - ref).astype(np.float32).tobytes()
+
+
 def test_long_window_rejects_wide_groups(torch_dev):
     """Shuffled times: each group's rows select frames from the whole
     sequence, more than 2048 of them, and nothing is written."""
