@@ -199,10 +199,21 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
   unsigned mask = 0u;
   bool single = false;                              // every pixel's bin holds one key
   constexpr int kDigitUnroll = PPK ? 1 : 4;
-#pragma unroll kDigitUnroll
-  for (int d = 3; d >= 0; --d) {
+  // With few keys per thread the histograms are cleared once: after each
+  // digit's scan every thread takes its own adds back, which costs VPT
+  // atomics instead of a pass over all sub-histograms and a barrier.
+  constexpr bool kUnadd = !PPK && VPT <= 8;
+  unsigned added[kUnadd ? VPT : 1];
+  if constexpr (kUnadd) {
     zero_hist();
     __syncthreads();
+  }
+#pragma unroll kDigitUnroll
+  for (int d = 3; d >= 0; --d) {
+    if constexpr (!kUnadd) {
+      zero_hist();
+      __syncthreads();
+    }
     const unsigned prefix = sh.prefix[t.px];
     const int shft = 8 * d;
 #pragma unroll
@@ -222,6 +233,7 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
         bin = part ? min((key[i] ^ prefix) >> shft, (unsigned)kBins) : (unsigned)kBins;
       }
       atomicAdd(&my_hist[bin], 1u);
+      if constexpr (kUnadd) added[i] = bin;
     }
     __syncthreads();
     // wave w scans the histogram of pixel w: lane l holds bins l, l+64, l+128, l+192
@@ -266,6 +278,12 @@ __device__ __forceinline__ void select_median(const Tile<kPix>& t, const unsigne
       if (most <= 1u) {                             // block-uniform
         single = true;
         break;
+      }
+      // every scan of this digit is done (barrier above): restore the zeros
+      // for the next digit, whose adds commute with these
+      if constexpr (kUnadd) {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) atomicSub(&my_hist[added[i]], 1u);
       }
     }
   }

@@ -109,7 +109,7 @@ def test_rotate_parity_large(torch_dev, T, N):
         assert _rel(out[t], ref) <= REL_L2
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 16, 17, 64, 65, 100, 1024, 4096])
+@pytest.mark.parametrize("T", [1, 2, 3, 16, 17, 64, 65, 100, 200, 500, 1024, 4096])
 def test_median_bit_exact(torch_dev, T):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
@@ -126,7 +126,7 @@ def test_median_bit_exact(torch_dev, T):
     assert got.tobytes() == ref.tobytes()
 
 
-@pytest.mark.parametrize("T", [2, 37, 64, 1000, 2049])
+@pytest.mark.parametrize("T", [2, 37, 64, 129, 300, 512, 1000, 2049])
 def test_median_bit_exact_ragged_and_degenerate(torch_dev, T):
     """A pixel count that leaves the last block partly empty, pixels whose
     values are all equal, nearly all equal, or two alternating values, beside
