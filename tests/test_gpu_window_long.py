@@ -71,7 +71,8 @@ def _check_all_modes(G, torch, dev, st, t, a, t_max, amin):
     return sel
 
 
-@pytest.mark.parametrize("T,N,t_max", [(2049, 6, 150.0), (2500, 6, 150.0), (2500, 8, 1400.0), (4100, 6, 150.0)])
+@pytest.mark.parametrize("T,N,t_max", [(2049, 6, 150.0), (2304, 6, 150.0), (2500, 6, 150.0), (2500, 8, 1400.0),
+                                       (4100, 6, 150.0)])
 def test_long_window_bit_exact(torch_dev, T, N, t_max):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
@@ -166,6 +167,12 @@ def test_long_adi_window_against_oracle(torch_dev):
     # without a PSF cube the PSF waits in the ring: the same result, bit for bit
     fin2 = G.adi_reduce_window(torch.from_numpy(cube).to(dev), dx, dy, pa, t, 150.0, 2.0)
     assert fin2.cpu().numpy().tobytes() == fin.cpu().numpy().tobytes()
+    # with the residual cube as output (the shifted frames, then their residuals, live there)
+    fin3, res = G.adi_reduce_window(torch.from_numpy(cube).to(dev), dx, dy, pa, t, 150.0, 2.0, residuals=True)
+    assert fin3.cpu().numpy().tobytes() == fin.cpu().numpy().tobytes()
+    r = res.cpu().numpy()
+    for i in (0, 1000, 2048, 2299):
+        assert np.linalg.norm(r[i] - ref["derotated"][i]) / scale <= 1e-5, i
 
 
 def test_long_window_maximum_frames(torch_dev):
