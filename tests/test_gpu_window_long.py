@@ -1,7 +1,8 @@
 """GPU: the per-frame PSF of Sect. 3.3 on sequences longer than 2048 frames.
 
 Such sequences run in groups of 256 consecutive frames; each group sorts only
-the frames its rows select.  The bar is the one of the short sequences: the
+the frames its rows select (lists of about 90 to 1660 frames here, so every
+per-group kernel width from 128 to 2048 keys runs).  The bar is the one of the short sequences: the
 per-frame medians bit-exact against the oracle's float32 medians of the
 oracle's own selection, residuals the float32 differences, in every output
 mode (PSF and residuals apart, residuals over the stack with and without a
@@ -71,8 +72,8 @@ def _check_all_modes(G, torch, dev, st, t, a, t_max, amin):
     return sel
 
 
-@pytest.mark.parametrize("T,N,t_max", [(2049, 6, 150.0), (2304, 6, 150.0), (2500, 6, 150.0), (2500, 8, 1400.0),
-                                       (4100, 6, 150.0)])
+@pytest.mark.parametrize("T,N,t_max", [(2049, 6, 150.0), (2304, 6, 150.0), (2500, 6, 150.0), (2500, 6, 600.0),
+                                       (2500, 8, 1400.0), (4100, 6, 150.0)])
 def test_long_window_bit_exact(torch_dev, T, N, t_max):
     torch, dev = torch_dev
     import paper_1510_04331_amd as G
@@ -82,7 +83,7 @@ def test_long_window_bit_exact(torch_dev, T, N, t_max):
     sel = _check_all_modes(G, torch, dev, st, t, a, t_max, 2.0)
     n_sel = sel.sum(axis=1)
     assert (n_sel < T).any()                              # real selections
-    if t_max < 1000.0:
+    if t_max < 300.0:
         assert (n_sel == T).any()                         # and rows that fall back to all frames
 
 
